@@ -1,0 +1,153 @@
+"""FP64 CPU oracle for the star-stencil wave path.
+
+TEST INFRASTRUCTURE ONLY: the plain, slow reference the GPU library is checked
+against.  Only the test suite, the smoke check and the benchmark's CPU-baseline
+leg may import it; the library itself never does.  It shares no code with the
+GPU path (it reads inputs from the seeded generators in ``synth`` only).
+
+The arithmetic lives in ``ref.c`` (plain C loop nests, FP64) and, for the
+low-precision storage emulation, in ``lowp.py`` (numpy).  ``brute.py`` is an
+independent pure-Python exact-rational stencil used to pin ``ref.c``.
+
+Parity pins: see tests/test_oracle_*.py.  Every function here is pinned by at
+least one property fixed by the mathematics (polynomial exactness, impulse
+response, symmetry, energy conservation, Fourier-mode recursion, exact
+rational brute force, finite differences); the FP16/BF16 emulation is pinned
+by exact small cases of its scale rule and rounding.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from .build import build_oracle, LIB_PATH
+
+HALO = 4
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        build_oracle()
+    lib = ctypes.CDLL(LIB_PATH)
+    i, d = ctypes.c_int, ctypes.c_double
+    lib.ref_laplacian.argtypes = [i, i, i, _dp, _dp, _dp]
+    lib.ref_laplacian.restype = None
+    lib.ref_stencil_apply.argtypes = [i, i, i, _dp, i, _dp, _dp]
+    lib.ref_stencil_apply.restype = i
+    lib.ref_wave_run.argtypes = [i, i, i, _dp, d, d, _dp, i, i, _ip, _dp, i, _ip, _dp, _dp, _dp]
+    lib.ref_wave_run.restype = None
+    lib.ref_energy.argtypes = [i, i, i, _dp, d, d, _dp, _dp, _dp]
+    lib.ref_energy.restype = d
+    lib.ref_adjoint_grad.argtypes = [i, i, i, _dp, d, d, _dp, i, i, _ip, _dp, i, _ip, _dp, _dp]
+    lib.ref_adjoint_grad.restype = d
+    lib.ref_num_threads.argtypes = []
+    lib.ref_num_threads.restype = i
+    _lib = lib
+    return lib
+
+
+def _p(a, t=_dp):
+    return a.ctypes.data_as(t)
+
+
+def coeff_vector(coeffs) -> np.ndarray:
+    """[c_xyz, c_x1..4, c_y1..4, c_z1..4] as FP64."""
+    c = np.empty(13, dtype=np.float64)
+    c[0] = coeffs["center"]
+    c[1:5] = coeffs["ax"]
+    c[5:9] = coeffs["ay"]
+    c[9:13] = coeffs["az"]
+    return c
+
+
+def padded(a, halo_value=0.0) -> np.ndarray:
+    """Interior (nz, ny, nx) -> FP64 padded array with a constant halo."""
+    a = np.asarray(a, dtype=np.float64)
+    out = np.full(tuple(s + 2 * HALO for s in a.shape), halo_value, dtype=np.float64)
+    out[HALO:-HALO, HALO:-HALO, HALO:-HALO] = a
+    return out
+
+
+def interior(p) -> np.ndarray:
+    return p[HALO:-HALO, HALO:-HALO, HALO:-HALO]
+
+
+def num_threads() -> int:
+    return _load().ref_num_threads()
+
+
+def laplacian(u_pad, coeffs) -> np.ndarray:
+    """L u on the interior (Eq. 3), reading the halo of the padded input.
+    Returns an interior (nz, ny, nx) FP64 array."""
+    u_pad = np.ascontiguousarray(u_pad, dtype=np.float64)
+    nz, ny, nx = (s - 2 * HALO for s in u_pad.shape)
+    out = np.zeros_like(u_pad)
+    _load().ref_laplacian(nx, ny, nz, _p(coeff_vector(coeffs)), _p(u_pad), _p(out))
+    return interior(out).copy()
+
+
+def stencil_apply(u_pad, v_pad, coeffs, sweeps: int):
+    """Ping-pong sweeps (paper's star2d4r listing).  Returns (u, v, in_v) as
+    padded FP64 arrays, in_v = 1 when the last result is in v."""
+    u = np.array(u_pad, dtype=np.float64, order="C")
+    v = np.array(v_pad, dtype=np.float64, order="C")
+    nz, ny, nx = (s - 2 * HALO for s in u.shape)
+    in_v = _load().ref_stencil_apply(nx, ny, nz, _p(coeff_vector(coeffs)), sweeps, _p(u), _p(v))
+    return u, v, in_v
+
+
+def wave_run(coeffs, v, dt, dx, nsteps, src=None, amp=None, rec=None, prev=None, cur=None):
+    """FP64 leapfrog run (Eq. 2, Algorithm 1).
+
+    v: interior (nz, ny, nx).  src (ns,3) int, amp (nsteps, ns); rec (nr,3).
+    prev/cur: optional padded initial states u^{-1}, u^0 (default zero).
+    Returns dict(prev=u^{N-1}, cur=u^N (padded FP64), traces (nsteps, nr)).
+    """
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    nz, ny, nx = v.shape
+    shp = (nz + 2 * HALO, ny + 2 * HALO, nx + 2 * HALO)
+    prev = np.zeros(shp) if prev is None else np.array(prev, dtype=np.float64, order="C")
+    cur = np.zeros(shp) if cur is None else np.array(cur, dtype=np.float64, order="C")
+    src = np.zeros((0, 3), np.int32) if src is None else np.ascontiguousarray(src, np.int32)
+    rec = np.zeros((0, 3), np.int32) if rec is None else np.ascontiguousarray(rec, np.int32)
+    ns, nr = len(src), len(rec)
+    amp = np.zeros((nsteps, max(ns, 1))) if amp is None else np.ascontiguousarray(amp, np.float64)
+    traces = np.zeros((nsteps, max(nr, 1)), dtype=np.float64)
+    _load().ref_wave_run(nx, ny, nz, _p(coeff_vector(coeffs)), float(dt), float(dx), _p(v),
+                         int(nsteps), ns, _p(src, _ip), _p(amp), nr, _p(rec, _ip), _p(traces),
+                         _p(prev), _p(cur))
+    return {"prev": prev, "cur": cur, "traces": traces[:, :nr]}
+
+
+def energy(coeffs, v, dt, dx, u0_pad, u1_pad) -> float:
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    nz, ny, nx = v.shape
+    u0 = np.ascontiguousarray(u0_pad, dtype=np.float64)
+    u1 = np.ascontiguousarray(u1_pad, dtype=np.float64)
+    return _load().ref_energy(nx, ny, nz, _p(coeff_vector(coeffs)), float(dt), float(dx),
+                              _p(v), _p(u0), _p(u1))
+
+
+def adjoint_grad(coeffs, v, dt, dx, nsteps, src, amp, rec, obs):
+    """Misfit J and dJ/dv (interior FP64) by the discrete adjoint."""
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    nz, ny, nx = v.shape
+    src = np.ascontiguousarray(src, np.int32)
+    rec = np.ascontiguousarray(rec, np.int32)
+    amp = np.ascontiguousarray(amp, np.float64)
+    obs = np.ascontiguousarray(obs, np.float64)
+    g = np.zeros((nz, ny, nx), dtype=np.float64)
+    J = _load().ref_adjoint_grad(nx, ny, nz, _p(coeff_vector(coeffs)), float(dt), float(dx),
+                                 _p(v), int(nsteps), len(src), _p(src, _ip), _p(amp),
+                                 len(rec), _p(rec, _ip), _p(obs), _p(g))
+    return J, g

@@ -1,0 +1,275 @@
+/*
+ * FP64 CPU oracle for the 25-point star stencil and the acoustic leapfrog.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow reference that the
+ * GPU library is checked against.  Only the test suite, the smoke check and
+ * the benchmark's CPU-baseline leg may load it.  It shares no code, header or
+ * constant with the GPU library.
+ *
+ * Layout: every field is a dense FP64 array of (nz+8) x (ny+8) x (nx+8)
+ * values, x fastest, with a 4-cell frame (the halo) on every face.  Interior
+ * point (x, y, z), 0 <= x < nx etc., lives at index
+ *     ((z+4) * (ny+8) + (y+4)) * (nx+8) + (x+4).
+ * The halo holds the boundary values (zero for the Dirichlet problems); the
+ * oracle reads it and never writes it.
+ *
+ * Coefficients: c[0] is the centre weight c_xyz; c[1..4] are c_x1..c_x4,
+ * c[5..8] are c_y1..c_y4 and c[9..12] are c_z1..c_z4 (the paper's Eq. 3).
+ *
+ * The loops over z may run in parallel (OpenMP); every output point is
+ * computed by one thread in a fixed order, so results do not depend on the
+ * thread count.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define H 4
+
+static inline int64_t at(int nx, int ny, int x, int y, int z)
+{
+    return ((int64_t)(z + H) * (ny + 2 * H) + (y + H)) * (int64_t)(nx + 2 * H) + (x + H);
+}
+
+static int64_t padded_count(int nx, int ny, int nz)
+{
+    return (int64_t)(nx + 2 * H) * (ny + 2 * H) * (nz + 2 * H);
+}
+
+/* Eq. 3: c_xyz u(i,j,k) + sum_{m=1..4} c_xm [u(i+m)+u(i-m)] + c_ym [...] + c_zm [...] */
+static double star25_at(int nx, int ny, const double *c, const double *u, int x, int y, int z)
+{
+    double s = c[0] * u[at(nx, ny, x, y, z)];
+    for (int m = 1; m <= 4; ++m) {
+        s += c[m] * (u[at(nx, ny, x + m, y, z)] + u[at(nx, ny, x - m, y, z)]);
+        s += c[4 + m] * (u[at(nx, ny, x, y + m, z)] + u[at(nx, ny, x, y - m, z)]);
+        s += c[8 + m] * (u[at(nx, ny, x, y, z + m)] + u[at(nx, ny, x, y, z - m)]);
+    }
+    return s;
+}
+
+/* out[interior] = L u, the 25-point star of Eq. 3 with the halo of u. */
+void ref_laplacian(int nx, int ny, int nz, const double *c, const double *u, double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x)
+                out[at(nx, ny, x, y, z)] = star25_at(nx, ny, c, u, x, y, z);
+}
+
+/*
+ * Repeated sweeps, ping-ponging two grids as in the paper's star2d4r listing:
+ * sweep s reads one grid and writes the other's interior, then the roles swap.
+ * Returns 0 if the last result is in u, 1 if it is in v.
+ */
+int ref_stencil_apply(int nx, int ny, int nz, const double *c, int sweeps, double *u, double *v)
+{
+    double *a = u, *b = v;
+    int in_v = 0;
+    for (int s = 0; s < sweeps; ++s) {
+        ref_laplacian(nx, ny, nz, c, a, b);
+        double *t = a; a = b; b = t;
+        in_v = !in_v;
+    }
+    return in_v;
+}
+
+/*
+ * Leapfrog run (Eq. 2 with the Laplacian of Eq. 3 at unit spacing, and the
+ * time loop of Algorithm 1).  For n = 0..nsteps-1:
+ *     u^{n+1} = 2 u^n - u^{n-1} + m (L u^n),     m = (v dt / dx)^2,
+ *     u^{n+1}[src_s] += dt^2 v[src_s]^2 amp[n][s]        (right-hand side),
+ *     traces[n][r] = u^{n+1}[rec_r].
+ * On entry prev = u^{-1}, cur = u^0 (padded); on return prev = u^{N-1},
+ * cur = u^N.  v is interior-dense (nz, ny, nx).  Halos of prev/cur are kept.
+ */
+void ref_wave_run(int nx, int ny, int nz, const double *c, double dt, double dx,
+                  const double *v, int nsteps,
+                  int nsrc, const int32_t *src, const double *amp,
+                  int nrec, const int32_t *rec, double *traces,
+                  double *prev, double *cur)
+{
+    const int64_t np = padded_count(nx, ny, nz);
+    double *lap = (double *)calloc((size_t)np, sizeof(double));
+    double *bufs[2] = {prev, cur};
+    int ip = 0, ic = 1;
+    const double r = dt / dx;
+    for (int n = 0; n < nsteps; ++n) {
+        double *up = bufs[ip], *uc = bufs[ic];
+        ref_laplacian(nx, ny, nz, c, uc, lap);
+#pragma omp parallel for schedule(static)
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) {
+                    int64_t i = at(nx, ny, x, y, z);
+                    double vv = v[((int64_t)z * ny + y) * nx + x];
+                    double m = (vv * r) * (vv * r);
+                    up[i] = 2.0 * uc[i] - up[i] + m * lap[i];
+                }
+        for (int s = 0; s < nsrc; ++s) {
+            int x = src[3 * s], y = src[3 * s + 1], z = src[3 * s + 2];
+            double vv = v[((int64_t)z * ny + y) * nx + x];
+            up[at(nx, ny, x, y, z)] += dt * dt * vv * vv * amp[(int64_t)n * nsrc + s];
+        }
+        for (int q = 0; q < nrec; ++q) {
+            int x = rec[3 * q], y = rec[3 * q + 1], z = rec[3 * q + 2];
+            traces[(int64_t)n * nrec + q] = up[at(nx, ny, x, y, z)];
+        }
+        int t = ip; ip = ic; ic = t;
+    }
+    /* the newest state is bufs[ic]; put u^N in cur and u^{N-1} in prev */
+    if (bufs[ic] != cur) {
+        double *tmp = (double *)malloc((size_t)np * sizeof(double));
+        memcpy(tmp, cur, (size_t)np * sizeof(double));
+        memcpy(cur, prev, (size_t)np * sizeof(double));
+        memcpy(prev, tmp, (size_t)np * sizeof(double));
+        free(tmp);
+    }
+    free(lap);
+}
+
+/*
+ * Discrete energy between two consecutive states u0 = u^n, u1 = u^{n+1}:
+ *     E = sum (u1 - u0)^2 / m  -  sum u1 (L u0),   m = (v dt / dx)^2.
+ * Conserved by the source-free leapfrog when L is symmetric (zero halo).
+ * Per-plane partial sums are added in plane order.
+ */
+double ref_energy(int nx, int ny, int nz, const double *c, double dt, double dx,
+                  const double *v, const double *u0, const double *u1)
+{
+    double *part = (double *)calloc((size_t)nz, sizeof(double));
+    const double r = dt / dx;
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < nz; ++z) {
+        double s = 0.0;
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                int64_t i = at(nx, ny, x, y, z);
+                double vv = v[((int64_t)z * ny + y) * nx + x];
+                double m = (vv * r) * (vv * r);
+                double d = u1[i] - u0[i];
+                s += d * d / m - u1[i] * star25_at(nx, ny, c, u0, x, y, z);
+            }
+        part[z] = s;
+    }
+    double e = 0.0;
+    for (int z = 0; z < nz; ++z) e += part[z];
+    free(part);
+    return e;
+}
+
+/*
+ * Misfit gradient by the discrete adjoint of the leapfrog, with every forward
+ * state kept in memory (for small grids).  Forward (ref_wave_run semantics)
+ * from zero states:
+ *     u^{n+1} = 2u^n - u^{n-1} + m (L u^n + dx^2 amp[n] e_src),  n = 0..N-1
+ * (so that m dx^2 amp = dt^2 v^2 amp is the injected value), traces
+ * d^n = R u^{n+1}.  Misfit J = 1/2 sum_n sum_r (R u^{n+1} - obs[n])^2.
+ * Adjoint, lambda^{N+1} = lambda^{N+2} = 0, for k = N..1:
+ *     lambda^k = 2 lambda^{k+1} - lambda^{k+2} + L(m lambda^{k+1}) + R^T r^k,
+ *     r^k = R u^k - obs[k-1].
+ * Gradient: dJ/dm = sum_{n=0}^{N-1} lambda^{n+1} (L u^n + dx^2 amp[n] e_src),
+ *           dJ/dv = dJ/dm * 2 m / v   (dt, dx held fixed).
+ * Returns J; grad_v is interior-dense (nz, ny, nx).
+ */
+double ref_adjoint_grad(int nx, int ny, int nz, const double *c, double dt, double dx,
+                        const double *v, int nsteps,
+                        int nsrc, const int32_t *src, const double *amp,
+                        int nrec, const int32_t *rec, const double *obs,
+                        double *grad_v)
+{
+    const int64_t np = padded_count(nx, ny, nz);
+    const int N = nsteps;
+    const double r = dt / dx;
+    /* m on the padded grid, zero on the halo */
+    double *m = (double *)calloc((size_t)np, sizeof(double));
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                double vv = v[((int64_t)z * ny + y) * nx + x];
+                m[at(nx, ny, x, y, z)] = (vv * r) * (vv * r);
+            }
+    /* all states u^{-1}..u^N: u[n+1] is u^n */
+    double *u = (double *)calloc((size_t)np * (N + 2), sizeof(double));
+    double *lap = (double *)calloc((size_t)np, sizeof(double));
+#define U(n) (u + (int64_t)((n) + 1) * np)
+    for (int n = 0; n < N; ++n) {
+        const double *uc = U(n), *up = U(n - 1);
+        double *un = U(n + 1);
+        ref_laplacian(nx, ny, nz, c, uc, lap);
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) {
+                    int64_t i = at(nx, ny, x, y, z);
+                    un[i] = 2.0 * uc[i] - up[i] + m[i] * lap[i];
+                }
+        for (int s = 0; s < nsrc; ++s) {
+            int64_t i = at(nx, ny, src[3 * s], src[3 * s + 1], src[3 * s + 2]);
+            un[i] += m[i] * dx * dx * amp[(int64_t)n * nsrc + s];
+        }
+    }
+    /* residuals and misfit */
+    double *res = (double *)calloc((size_t)N * (nrec > 0 ? nrec : 1), sizeof(double));
+    double J = 0.0;
+    for (int k = 1; k <= N; ++k)
+        for (int q = 0; q < nrec; ++q) {
+            double d = U(k)[at(nx, ny, rec[3 * q], rec[3 * q + 1], rec[3 * q + 2])]
+                       - obs[(int64_t)(k - 1) * nrec + q];
+            res[(int64_t)(k - 1) * nrec + q] = d;
+            J += 0.5 * d * d;
+        }
+    /* adjoint sweep */
+    double *l1 = (double *)calloc((size_t)np, sizeof(double)); /* lambda^{k+1} */
+    double *l2 = (double *)calloc((size_t)np, sizeof(double)); /* lambda^{k+2} */
+    double *l0 = (double *)calloc((size_t)np, sizeof(double)); /* lambda^k     */
+    double *ml = (double *)calloc((size_t)np, sizeof(double));
+    double *gm = (double *)calloc((size_t)np, sizeof(double));
+    for (int k = N; k >= 1; --k) {
+        for (int64_t i = 0; i < np; ++i) ml[i] = m[i] * l1[i];
+        ref_laplacian(nx, ny, nz, c, ml, lap);
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) {
+                    int64_t i = at(nx, ny, x, y, z);
+                    l0[i] = 2.0 * l1[i] - l2[i] + lap[i];
+                }
+        for (int q = 0; q < nrec; ++q)
+            l0[at(nx, ny, rec[3 * q], rec[3 * q + 1], rec[3 * q + 2])] +=
+                res[(int64_t)(k - 1) * nrec + q];
+        /* dJ/dm += lambda^k (L u^{k-1} + dx^2 amp[k-1] e_src) */
+        ref_laplacian(nx, ny, nz, c, U(k - 1), lap);
+        for (int s = 0; s < nsrc; ++s) {
+            int64_t i = at(nx, ny, src[3 * s], src[3 * s + 1], src[3 * s + 2]);
+            lap[i] += dx * dx * amp[(int64_t)(k - 1) * nsrc + s];
+        }
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) {
+                    int64_t i = at(nx, ny, x, y, z);
+                    gm[i] += l0[i] * lap[i];
+                }
+        double *t = l2; l2 = l1; l1 = l0; l0 = t;
+    }
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                int64_t i = at(nx, ny, x, y, z);
+                double vv = v[((int64_t)z * ny + y) * nx + x];
+                grad_v[((int64_t)z * ny + y) * nx + x] = gm[i] * 2.0 * m[i] / vv;
+            }
+#undef U
+    free(m); free(u); free(lap); free(res); free(l1); free(l2); free(l0); free(ml); free(gm);
+    return J;
+}
+
+int ref_num_threads(void)
+{
+#ifdef _OPENMP
+    extern int omp_get_max_threads(void);
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
