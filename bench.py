@@ -1,0 +1,209 @@
+#!/usr/bin/env python3
+"""Benchmark: FP32 acoustic leapfrog with the 25-point star on one MI355X.
+
+Workload (one benchmark step = one complete simulation): 1024 x 1024 x 512
+interior, 4-cell zero Dirichlet halo, layered velocity model (8 horizontal
+layers, speeds U[1500, 4500] m/s, seed 0), dx = 10 m, dt at CFL 0.4, Ricker
+15 Hz source at the grid centre, 500 time steps from zero wavefields; three
+FP32 fields resident (p, p_prev/p_next, v).
+
+Prints one JSON line: GPts/s (point-updates per second), the HBM roofline
+of the dominant kernel measured with HIP events on the launch stream, and the
+FP64 CPU oracle timed on the host cores on a bounded sample of the workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GPts/s + % HBM roofline, 25-pt star FP32 vs FP16-store; p50/p99 shot latency"
+HBM_PEAK_GBS = 8000.0
+NX, NY, NZ, NSTEPS = 1024, 1024, 512, 500
+BYTES_PER_POINT = 16          # read p, p_prev, v; write p_next (FP32)
+FLOPS_PER_POINT = 49          # paper's 2*points-1 convention for star3d4r
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("star25.hip", "internal.h", "api.cpp"):
+        with open(os.path.join(ROOT, "paper_2309_04671_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "k_star25_wave_1024x1024x512_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(min_seconds=10.0):
+    """The FP64 oracle on a 1024 x 1024 x 128 slab of the same model (same
+    per-point work), stepping until at least min_seconds of CPU work."""
+    import numpy as np
+    import oracle
+    import synth
+    nx, ny, nz = NX, NY, 128
+    v = synth.layered_velocity(nx, ny, nz, 0)
+    dx = 10.0
+    dt = synth.cfl_dt(v, dx)
+    co = synth.star25_coeffs()
+    src = np.array([[nx // 2, ny // 2, nz // 2]], np.int32)
+    prev = np.zeros((nz + 8, ny + 8, nx + 8))
+    cur = np.zeros_like(prev)
+    w = synth.ricker(64, dt)
+    steps, elapsed = 0, 0.0
+    while elapsed < min_seconds and steps < 64:
+        t0 = time.perf_counter()
+        r = oracle.wave_run(co, v, dt, dx, 2, src=src, amp=w[steps:steps + 2, None], prev=prev, cur=cur)
+        elapsed += time.perf_counter() - t0
+        prev, cur = r["prev"], r["cur"]
+        steps += 2
+    pts = nx * ny * nz * steps
+    return {"value": round(pts / elapsed / 1e9, 4), "unit": "GPts/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "%dx%dx%d slab of the same layered model, %d FP64 leapfrog steps, %.1f s"
+                      % (nx, ny, nz, steps, elapsed)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5, help="timed simulations (500 time steps each)")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--nt", type=int, default=NSTEPS,
+                    help="time steps per simulation (default: the workload's 500; fewer only for "
+                         "profiling runs)")
+    ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
+                    help="instead of the benchmark, copy a GIB-sized buffer 4 times with torch "
+                         "(reference kernel for the HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the library runs on a single MI355X and has no "
+              "multi-GPU path (--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_2309_04671_amd import fields, lib
+
+    lib.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    if args.calibrate_copy > 0:
+        n = int(args.calibrate_copy * (1 << 30))
+        a = torch.ones(n, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(4):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "torch copy", "bytes_read_per_launch": n,
+                          "bytes_written_per_launch": n, "launches": 4}))
+        return
+    nt = args.nt
+
+    log("setting up %dx%dx%d" % (NX, NY, NZ))
+    g = lib.grid_init(NX, NY, NZ, lib.SP_F32)
+    vel = synth.layered_velocity(NX, NY, NZ, 0)
+    dx = 10.0
+    dt = synth.cfl_dt(vel, dx)
+    V = fields.Field(g).set_interior(vel)
+    del vel
+    P, C = fields.Field(g), fields.Field(g)
+    w = synth.ricker(nt, dt, 15.0)
+    amp = torch.tensor(w[:, None], dtype=torch.float32, device=dev)
+    src = lib.make_sources([[NX // 2, NY // 2, NZ // 2]], amp.data_ptr(), 1)
+    co = lib.coeffs(synth.star25_coeffs())
+    ev = []
+
+    def simulate(timed):
+        P.buf.zero_()
+        C.buf.zero_()
+        st = lib.sp_wave_state(C.ptr, P.ptr, None, 0)
+        if timed:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+        lib.sp_wave_step(g, co, dt, dx, g, V.ptr, st, nt, src=src, stream=stream)
+        if timed:
+            e1.record(stream)
+            ev.append((e0, e1))
+        return st
+
+    for i in range(args.warmup):
+        simulate(False)
+        torch.cuda.synchronize()
+        log("warmup %d done" % i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        st = simulate(True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    log("timed %d simulations in %.3f s" % (args.steps, wall))
+    final = (P if st.cur == P.ptr else C).interior()
+    if not bool(torch.isfinite(final).all()):
+        raise RuntimeError("non-finite wavefield")
+
+    npts = NX * NY * NZ
+    gpts = npts * nt * args.steps / wall / 1e9
+    kern_ms = sum(a.elapsed_time(b) for a, b in ev)      # event pairs on the launch stream
+    launch_s = kern_ms / 1e3 / (nt * args.steps)
+    achieved = BYTES_PER_POINT * npts / launch_s / 1e9
+    traffic = measured_traffic()
+
+    out = {
+        "metric": METRIC,
+        "value": round(gpts, 3),
+        "unit": "GPts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "acoustic leapfrog, 25-point star, %dx%dx%d FP32, %d time steps, "
+                               "layered v (8 layers, seed 0), Ricker 15 Hz at centre, CFL 0.4"
+                               % (NX, NY, NZ, nt),
+                   "grid": [NX, NY, NZ], "time_steps": nt, "global_batch": 1,
+                   "step": "one full simulation"},
+        "roofline": {"bound": "hbm", "kernel": "k_star25<64,16,WAVE>",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "avg_launch_us": round(launch_s * 1e6, 2),
+                     "bytes_per_launch": BYTES_PER_POINT * npts},
+        "hbm_frac_of_wall": round(gpts * BYTES_PER_POINT / HBM_PEAK_GBS, 4),
+        "gflops": round(gpts * FLOPS_PER_POINT, 1),
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

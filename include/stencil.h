@@ -1,0 +1,171 @@
+/*
+ * libstencil: 25-point star stencil and acoustic leapfrog on gfx950 (MI355X).
+ *
+ * The operations are those of the paper "StencilPy" (arXiv 2309.04671):
+ *   - the 25-point star-shaped high-order stencil of Sec. 2.2, Eq. 3
+ *     (radius 4 along x, y and z around a centre point),
+ *   - the constant-density acoustic isotropic leapfrog of Sec. 2.2, Eq. 2
+ *     (u^{n+1} = 2u^n - u^{n-1} + dt^2 V^2 lap u^n + dt^2 V^2 f^n),
+ *   - the time loop of Algorithm 1 (update every point, then add the source),
+ * plus the discrete adjoint of that leapfrog for a receiver misfit, wavefield
+ * storage in FP16/BF16 with per-slab scales, and a continuous-batching shot
+ * queue.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Return value: SP_OK (0) or an SP_E* code.  On error nothing has been
+ *    enqueued; sp_last_error() returns a thread-local message.
+ *  - Every data pointer is a DEVICE pointer owned by the caller, unless the
+ *    comment says HOST.  The library never allocates device memory outside
+ *    a caller-provided workspace.
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).  All
+ *    compute calls are asynchronous on that stream; a device fault surfaces at
+ *    the next synchronisation.
+ *  - Axes: x is contiguous (the paper's i), then y (j), then z (k, depth; the
+ *    streaming axis).  Interior indices run 0..n-1; the halo is 4 cells wide
+ *    on every face (the stencil radius; the paper's "order").  The library
+ *    reads halo cells and never writes them: callers set them (zero for the
+ *    Dirichlet boundary) once after allocation.
+ */
+#ifndef SP_STENCIL_H
+#define SP_STENCIL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define SP_OK           0
+#define SP_EINVAL       1  /* bad argument (shape, halo, pointer, alignment, aliasing) */
+#define SP_EUNSUPPORTED 2  /* valid request this build does not implement */
+#define SP_EDEVICE      3  /* HIP runtime error */
+#define SP_ENOMEM       4  /* caller workspace / arena too small */
+#define SP_EBUDGET      5  /* shot can never fit the queue's HBM budget */
+#define SP_EPENDING     6  /* poll: shot not finished yet */
+#define SP_ENUMERIC     7  /* non-finite value detected */
+
+/* storage types */
+#define SP_F32  0
+#define SP_F16  1
+#define SP_BF16 2
+
+#define SP_HALO 4            /* the only supported halo width (radius 4) */
+#define SP_MAX_SOURCES 16    /* sources per wave_step call */
+#define SP_SLAB 16           /* planes per z-slab for FP16/BF16 scales */
+
+/*
+ * Grid descriptor: where each cell of a halo-padded field lives.
+ * Cell (x, y, z), -4 <= x < nx+4 (same for y, z), is element
+ *     origin + z * pitch_y * pitch_x + y * pitch_x + x
+ * of an allocation of `bytes` bytes.  Interior x = 0 of every row is
+ * 128-byte aligned; the 4 right-halo cells of a row share the (otherwise
+ * unused) lead padding of the next row.  Element offsets of different cells
+ * are distinct.
+ */
+typedef struct {
+    int32_t nx, ny, nz;     /* interior points */
+    int32_t halo;           /* = SP_HALO */
+    int32_t dtype;          /* SP_F32 / SP_F16 / SP_BF16 */
+    int32_t elem_bytes;     /* 4 or 2 */
+    int64_t pitch_x;        /* elements per padded row */
+    int64_t pitch_y;        /* rows per padded plane (ny + 8) */
+    int64_t planes;         /* padded planes (nz + 8) */
+    int64_t origin;         /* element offset of interior (0, 0, 0) */
+    int64_t elems;          /* elements to allocate */
+    int64_t bytes;          /* bytes to allocate (multiple of 256) */
+} sp_grid;
+
+/* Fill `out` for an nx x ny x nz interior.  halo must be 4.  Host-only. */
+int sp_grid_init(int nx, int ny, int nz, int halo, int dtype, sp_grid *out);
+
+/*
+ * Stencil weights of Eq. 3 at unit spacing: centre c_xyz and c_xm, c_ym, c_zm
+ * for m = 1..4.  Given in FP64; the kernels use them rounded once to FP32.
+ */
+typedef struct {
+    double center;
+    double ax[4], ay[4], az[4];
+} sp_coeffs;
+
+/*
+ * sp_stencil_apply -- `sweeps` sweeps of the star stencil (Eq. 3), FP32 only.
+ * Sweep s reads one grid and writes the other's interior, then the two swap
+ * roles, as in the paper's star2d4r listing (Sec. 5): after an odd number of
+ * sweeps the result is in v, after an even number in u; *result_in is set to
+ * 1 or 0 accordingly (HOST int).  u and v: allocations of g->bytes, distinct.
+ * sweeps >= 0 (0 is a no-op with *result_in = 0).
+ */
+int sp_stencil_apply(const sp_grid *g, const sp_coeffs *c, int sweeps,
+                     void *u, void *v, int *result_in, void *stream);
+
+/*
+ * Wavefield state of the leapfrog.  cur = u^n, prev = u^{n-1}; a step writes
+ * u^{n+1} over prev and swaps the two pointers, so on return cur is the
+ * newest state.  For FP16/BF16 grids `meta` points at sp_wave_meta_bytes()
+ * bytes of per-slab records (scales and maxima; zero-filled by the caller
+ * before the first step of zero fields); it must be NULL for FP32.
+ * `step` counts steps taken; it indexes the source amplitudes.
+ */
+typedef struct {
+    void *cur;
+    void *prev;
+    void *meta;
+    int64_t step;
+} sp_wave_state;
+
+/* Bytes of the FP16/BF16 metadata block for grid g (0 for FP32). Host-only. */
+int64_t sp_wave_meta_bytes(const sp_grid *g);
+
+/*
+ * Point sources (Eq. 2 right-hand side, added after the update as in
+ * Algorithm 1): after step n computes u^{n+1},
+ *     u^{n+1}[x_s] += dt^2 * v[x_s]^2 * amp[n * amp_stride + s].
+ * xyz is a HOST array (copied by value); amp is DEVICE FP32, indexed by the
+ * state's step counter.  n <= SP_MAX_SOURCES; points must lie in the interior.
+ */
+typedef struct {
+    int32_t n;
+    int32_t xyz[SP_MAX_SOURCES][3];
+    const float *amp;
+    int64_t amp_stride;
+} sp_sources;
+
+/*
+ * Receivers: after step n (and its source injection)
+ *     traces[(n - step0) * trace_stride + r] = u^{n+1}[x_r],
+ * where step0 is the state's step counter on entry.  xyz is DEVICE int32
+ * [n][3]; points outside the interior record 0.  traces is DEVICE FP32.
+ */
+typedef struct {
+    int32_t n;
+    const int32_t *xyz;
+    float *traces;
+    int64_t trace_stride;
+} sp_receivers;
+
+/*
+ * sp_wave_step -- `nsteps` leapfrog steps (Eq. 2 with Eq. 3 at spacing dx):
+ *     u^{n+1} = 2u^n - u^{n-1} + m * (L u^n),   m = (v * dt / dx)^2,
+ * then sources, then receivers.  v is an FP32 field on its own grid
+ * descriptor gv (same nx, ny, nz, dtype SP_F32).  src and rec may be NULL.
+ * The state's pointers are swapped once per step and its step counter
+ * advanced, before the call returns (the work itself is asynchronous).
+ */
+int sp_wave_step(const sp_grid *g, const sp_coeffs *c, double dt, double dx,
+                 const sp_grid *gv, const float *v, sp_wave_state *st, int nsteps,
+                 const sp_sources *src, const sp_receivers *rec, void *stream);
+
+/* Thread-local message for the last error on this thread ("" if none). */
+const char *sp_last_error(void);
+
+/* Library version string. */
+const char *sp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SP_STENCIL_H */

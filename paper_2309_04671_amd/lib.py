@@ -1,0 +1,161 @@
+"""ctypes binding of libstencil (include/stencil.h): same names, same structs.
+
+Argument marshalling only.  The shared library must have been built
+(``python -m paper_2309_04671_amd.build`` or ``__graft_entry__.build()``);
+loading fails loudly otherwise -- there is no fallback implementation.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libstencil.so")
+
+SP_OK, SP_EINVAL, SP_EUNSUPPORTED, SP_EDEVICE, SP_ENOMEM, SP_EBUDGET, SP_EPENDING, SP_ENUMERIC = range(8)
+SP_F32, SP_F16, SP_BF16 = 0, 1, 2
+SP_HALO = 4
+SP_MAX_SOURCES = 16
+SP_SLAB = 16
+
+ERROR_NAMES = {0: "SP_OK", 1: "SP_EINVAL", 2: "SP_EUNSUPPORTED", 3: "SP_EDEVICE",
+               4: "SP_ENOMEM", 5: "SP_EBUDGET", 6: "SP_EPENDING", 7: "SP_ENUMERIC"}
+
+# Every symbol include/stencil.h declares (checked by the ABI tests).
+EXPORTS = [
+    "sp_grid_init", "sp_stencil_apply", "sp_wave_meta_bytes", "sp_wave_step",
+    "sp_last_error", "sp_version",
+]
+
+
+class SpError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (ERROR_NAMES.get(code, str(code)), msg))
+        self.code = code
+
+
+class sp_grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("halo", ctypes.c_int32), ("dtype", ctypes.c_int32), ("elem_bytes", ctypes.c_int32),
+                ("pitch_x", ctypes.c_int64), ("pitch_y", ctypes.c_int64), ("planes", ctypes.c_int64),
+                ("origin", ctypes.c_int64), ("elems", ctypes.c_int64), ("bytes", ctypes.c_int64)]
+
+
+class sp_coeffs(ctypes.Structure):
+    _fields_ = [("center", ctypes.c_double), ("ax", ctypes.c_double * 4),
+                ("ay", ctypes.c_double * 4), ("az", ctypes.c_double * 4)]
+
+
+class sp_wave_state(ctypes.Structure):
+    _fields_ = [("cur", ctypes.c_void_p), ("prev", ctypes.c_void_p), ("meta", ctypes.c_void_p),
+                ("step", ctypes.c_int64)]
+
+
+class sp_sources(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("xyz", (ctypes.c_int32 * 3) * SP_MAX_SOURCES),
+                ("amp", ctypes.c_void_p), ("amp_stride", ctypes.c_int64)]
+
+
+class sp_receivers(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("xyz", ctypes.c_void_p), ("traces", ctypes.c_void_p),
+                ("trace_stride", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def load():
+    """Load libstencil.so; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libstencil.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp, i, d, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int64
+    lib.sp_grid_init.argtypes = [i, i, i, i, i, P(sp_grid)]
+    lib.sp_stencil_apply.argtypes = [P(sp_grid), P(sp_coeffs), i, vp, vp, P(ctypes.c_int), vp]
+    lib.sp_wave_meta_bytes.argtypes = [P(sp_grid)]
+    lib.sp_wave_meta_bytes.restype = i64
+    lib.sp_wave_step.argtypes = [P(sp_grid), P(sp_coeffs), d, d, P(sp_grid), vp, P(sp_wave_state), i,
+                                 P(sp_sources), P(sp_receivers), vp]
+    lib.sp_last_error.restype = ctypes.c_char_p
+    lib.sp_version.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        fn = getattr(lib, name)
+        if name in ("sp_grid_init", "sp_stencil_apply", "sp_wave_step"):
+            fn.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def check(rc):
+    if rc != SP_OK:
+        raise SpError(rc, load().sp_last_error().decode())
+    return rc
+
+
+def last_error() -> str:
+    return load().sp_last_error().decode()
+
+
+def grid_init(nx, ny, nz, dtype=SP_F32, halo=SP_HALO) -> sp_grid:
+    g = sp_grid()
+    check(load().sp_grid_init(nx, ny, nz, halo, dtype, ctypes.byref(g)))
+    return g
+
+
+def coeffs(d) -> sp_coeffs:
+    """Build sp_coeffs from {'center', 'ax', 'ay', 'az'}."""
+    c = sp_coeffs()
+    c.center = float(d["center"])
+    for k in ("ax", "ay", "az"):
+        arr = getattr(c, k)
+        for j in range(4):
+            arr[j] = float(d[k][j])
+    return c
+
+
+def stream_ptr(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def sp_stencil_apply(g, c, sweeps, u, v, stream=None) -> int:
+    """u, v: device pointers (int).  Returns result_in."""
+    out = ctypes.c_int(-1)
+    check(load().sp_stencil_apply(ctypes.byref(g), ctypes.byref(c), int(sweeps), ctypes.c_void_p(u),
+                                  ctypes.c_void_p(v), ctypes.byref(out), stream_ptr(stream)))
+    return out.value
+
+
+def make_sources(xyz, amp_ptr, amp_stride) -> sp_sources:
+    s = sp_sources()
+    s.n = len(xyz)
+    if s.n > SP_MAX_SOURCES:
+        raise ValueError("at most %d sources" % SP_MAX_SOURCES)
+    for k, p in enumerate(xyz):
+        for j in range(3):
+            s.xyz[k][j] = int(p[j])
+    s.amp = amp_ptr
+    s.amp_stride = int(amp_stride)
+    return s
+
+
+def make_receivers(n, xyz_ptr, traces_ptr, trace_stride) -> sp_receivers:
+    r = sp_receivers()
+    r.n = int(n)
+    r.xyz = xyz_ptr
+    r.traces = traces_ptr
+    r.trace_stride = int(trace_stride)
+    return r
+
+
+def sp_wave_step(g, c, dt, dx, gv, v_ptr, state, nsteps, src=None, rec=None, stream=None):
+    check(load().sp_wave_step(ctypes.byref(g), ctypes.byref(c), float(dt), float(dx), ctypes.byref(gv),
+                              ctypes.c_void_p(v_ptr), ctypes.byref(state), int(nsteps),
+                              ctypes.byref(src) if src is not None else None,
+                              ctypes.byref(rec) if rec is not None else None, stream_ptr(stream)))

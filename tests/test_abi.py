@@ -1,0 +1,125 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, lays grids out as documented, and rejects bad arguments
+before touching the device."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2309_04671_amd import lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "stencil.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sp_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    assert declared_functions() == sorted(lib.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = lib.load()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    assert L.sp_version().decode().startswith("libstencil")
+
+
+@pytest.mark.parametrize("dtype,eb", [(lib.SP_F32, 4), (lib.SP_F16, 2), (lib.SP_BF16, 2)])
+@pytest.mark.parametrize("shape", [(1, 1, 1), (64, 64, 64), (70, 37, 23), (1024, 1024, 512)])
+def test_grid_layout(shape, dtype, eb):
+    nx, ny, nz = shape
+    g = lib.grid_init(nx, ny, nz, dtype)
+    assert g.elem_bytes == eb and g.halo == 4
+    assert g.pitch_y == ny + 8 and g.planes == nz + 8
+    # interior x = 0 of every row is 128-byte aligned
+    assert (g.origin * eb) % 128 == 0 and (g.pitch_x * eb) % 128 == 0
+    # the left halo and the previous row's right halo fit in the lead pad
+    lead = g.origin - (4 * g.pitch_y + 4) * g.pitch_x
+    assert lead >= 8 and g.pitch_x >= lead + nx
+    # every padded cell is a distinct element inside the allocation
+    sz, sy = g.pitch_x * g.pitch_y, g.pitch_x
+    first = g.origin - 4 * sz - 4 * sy - 4
+    last = g.origin + (nz + 3) * sz + (ny + 3) * sy + (nx + 3)
+    assert first >= 0 and last < g.elems and g.elems * eb <= g.bytes
+    assert g.bytes % 256 == 0
+    # row y's right halo ends before row y+1's left halo starts
+    assert (nx + 3) < sy - 4
+
+
+def test_grid_init_rejects_bad_arguments():
+    L = lib.load()
+    g = lib.sp_grid()
+    assert L.sp_grid_init(8, 8, 8, 3, lib.SP_F32, ctypes.byref(g)) == lib.SP_EINVAL
+    assert "halo" in lib.last_error()
+    assert L.sp_grid_init(0, 8, 8, 4, lib.SP_F32, ctypes.byref(g)) == lib.SP_EINVAL
+    assert L.sp_grid_init(8, 8, 8, 4, 7, ctypes.byref(g)) == lib.SP_EINVAL
+    assert L.sp_grid_init(8, 8, 8, 4, lib.SP_F32, None) == lib.SP_EINVAL
+
+
+def test_apply_validates_before_launch():
+    L = lib.load()
+    g = lib.grid_init(16, 16, 16)
+    c = lib.coeffs({"center": -1, "ax": [0] * 4, "ay": [0] * 4, "az": [0] * 4})
+    out = ctypes.c_int()
+    # overlapping u and v
+    rc = L.sp_stencil_apply(ctypes.byref(g), ctypes.byref(c), 1, ctypes.c_void_p(4096),
+                            ctypes.c_void_p(4096 + 256), ctypes.byref(out), None)
+    assert rc == lib.SP_EINVAL and "overlap" in lib.last_error()
+    # misaligned pointer
+    rc = L.sp_stencil_apply(ctypes.byref(g), ctypes.byref(c), 1, ctypes.c_void_p(4100),
+                            ctypes.c_void_p(1 << 40), ctypes.byref(out), None)
+    assert rc == lib.SP_EINVAL and "aligned" in lib.last_error()
+    # descriptor not from sp_grid_init
+    bad = lib.grid_init(16, 16, 16)
+    bad.pitch_x += 1
+    rc = L.sp_stencil_apply(ctypes.byref(bad), ctypes.byref(c), 1, ctypes.c_void_p(1 << 30),
+                            ctypes.c_void_p(1 << 40), ctypes.byref(out), None)
+    assert rc == lib.SP_EINVAL and "sp_grid_init" in lib.last_error()
+    # FP16 grids are not supported by apply
+    h = lib.grid_init(16, 16, 16, lib.SP_F16)
+    rc = L.sp_stencil_apply(ctypes.byref(h), ctypes.byref(c), 1, ctypes.c_void_p(1 << 30),
+                            ctypes.c_void_p(1 << 40), ctypes.byref(out), None)
+    assert rc == lib.SP_EUNSUPPORTED
+    # negative sweeps
+    rc = L.sp_stencil_apply(ctypes.byref(g), ctypes.byref(c), -1, ctypes.c_void_p(1 << 30),
+                            ctypes.c_void_p(1 << 40), ctypes.byref(out), None)
+    assert rc == lib.SP_EINVAL
+
+
+def test_wave_step_validates_before_launch():
+    L = lib.load()
+    g = lib.grid_init(32, 32, 32)
+    gv = lib.grid_init(32, 32, 32)
+    c = lib.coeffs({"center": -1, "ax": [0] * 4, "ay": [0] * 4, "az": [0] * 4})
+    st = lib.sp_wave_state(1 << 30, 1 << 36, None, 0)
+    v = ctypes.c_void_p(1 << 40)
+
+    def call(**kw):
+        a = dict(g=g, gv=gv, dt=1e-3, dx=10.0, st=st, n=1, src=None, rec=None)
+        a.update(kw)
+        return L.sp_wave_step(ctypes.byref(a["g"]), ctypes.byref(c), a["dt"], a["dx"],
+                              ctypes.byref(a["gv"]), v, ctypes.byref(a["st"]), a["n"],
+                              ctypes.byref(a["src"]) if a["src"] is not None else None,
+                              ctypes.byref(a["rec"]) if a["rec"] is not None else None, None)
+
+    assert call(gv=lib.grid_init(32, 32, 31)) == lib.SP_EINVAL
+    assert call(dt=0.0) == lib.SP_EINVAL
+    assert call(n=-1) == lib.SP_EINVAL
+    assert call(st=lib.sp_wave_state(1 << 30, (1 << 30) + 512, None, 0)) == lib.SP_EINVAL
+    src = lib.make_sources([[40, 1, 1]], 1 << 20, 1)
+    assert call(src=src) == lib.SP_EINVAL and "outside" in lib.last_error()
+    src = lib.make_sources([[4, 1, 1]], None, 1)
+    assert call(src=src) == lib.SP_EINVAL
+    rec = lib.make_receivers(5, None, None, 5)
+    assert call(rec=rec) == lib.SP_EINVAL
+    rec = lib.make_receivers(5, 1 << 20, 1 << 21, 4)
+    assert call(rec=rec) == lib.SP_EINVAL
+    # the state must be untouched by a rejected call
+    assert st.cur == 1 << 30 and st.step == 0
