@@ -190,7 +190,7 @@ def main():
                                % (NX, NY, NZ, nt),
                    "grid": [NX, NY, NZ], "time_steps": nt, "global_batch": 1,
                    "step": "one full simulation"},
-        "roofline": {"bound": "hbm", "kernel": "k_star25<64,16,WAVE>",
+        "roofline": {"bound": "hbm", "kernel": "k_star25 (WAVE)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,

@@ -67,15 +67,16 @@ void fill_tiling(sp::SweepArgs &a, const sp::TileCfg &t) {
 
 sp::TileCfg tiles_for(const sp_grid *g) {
     sp::TileCfg t = sp::choose_tiles(g->nx, g->ny, g->nz);
-    // Optional override for tuning: SP_TILE=TXxTY[xZC]
+    // Optional override for tuning: SP_TILE=TXxTYxRY[xZC]
     if (const char *e = std::getenv("SP_TILE")) {
-        int tx = 0, ty = 0, zc = 0;
-        const int n = std::sscanf(e, "%dx%dx%d", &tx, &ty, &zc);
-        if (n >= 2) {
+        int tx = 0, ty = 0, ry = 0, zc = 0;
+        const int n = std::sscanf(e, "%dx%dx%dx%d", &tx, &ty, &ry, &zc);
+        if (n >= 3) {
             t.tx = tx;
             t.ty = ty;
+            t.ry = ry;
         }
-        if (n == 3 && zc > 0) t.zchunk = std::min(zc, g->nz);
+        if (n == 4 && zc > 0) t.zchunk = std::min(zc, g->nz);
     }
     return t;
 }

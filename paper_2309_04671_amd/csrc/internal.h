@@ -46,6 +46,7 @@ struct SweepArgs {
 // Launch configuration chosen by the host for a grid shape.
 struct TileCfg {
     int tx, ty;          // tile extent in x (points) and y (rows)
+    int ry;              // adjacent rows per thread
     int zchunk;          // planes per block
 };
 

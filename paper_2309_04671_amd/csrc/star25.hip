@@ -28,12 +28,19 @@ namespace sp {
 
 namespace {
 
-__device__ __forceinline__ float4 ld4(const float *p) {
-    return *reinterpret_cast<const float4 *>(p);
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f4v ld4(const float *p) {
+    return *reinterpret_cast<const f4v *>(p);
 }
 
-__device__ __forceinline__ void st4(float *p, float4 v) {
-    *reinterpret_cast<float4 *>(p) = v;
+// Streamed-once data: non-temporal hint keeps it from displacing reused lines.
+__device__ __forceinline__ f4v ld4_nt(const float *p) {
+    return __builtin_nontemporal_load(reinterpret_cast<const f4v *>(p));
+}
+
+__device__ __forceinline__ void st4_nt(float *p, f4v v) {
+    __builtin_nontemporal_store(v, reinterpret_cast<f4v *>(p));
 }
 
 // Barrier that orders LDS traffic only; pending global loads stay in flight.
@@ -43,20 +50,6 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-__device__ __forceinline__ float4 f4(float a) { return make_float4(a, a, a, a); }
-
-__device__ __forceinline__ float4 fma4(float c, float4 a, float4 acc) {
-    acc.x = fmaf(c, a.x, acc.x);
-    acc.y = fmaf(c, a.y, acc.y);
-    acc.z = fmaf(c, a.z, acc.z);
-    acc.w = fmaf(c, a.w, acc.w);
-    return acc;
-}
-
-__device__ __forceinline__ float4 add4(float4 a, float4 b) {
-    return make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
-}
-
 // Map a block index to a tile index so that each XCD receives one contiguous
 // range of tiles.  Bijective on [0, n) for any n.
 __device__ __forceinline__ int xcd_tile(int bid, int n) {
@@ -64,16 +57,21 @@ __device__ __forceinline__ int xcd_tile(int bid, int n) {
     return xcd * q + (xcd < r ? xcd : r) + loc;
 }
 
-template <int TX, int TY, int MODE>
-__global__ void __launch_bounds__((TX / 4) * TY)
+// One sweep over the block's tile and z-chunk.
+//   TX: tile width in points (4 per lane), TY: tile height in rows,
+//   RY: adjacent rows per thread (register blocking in y).
+template <int TX, int TY, int RY, int MODE>
+__global__ void __launch_bounds__((TX / 4) * (TY / RY))
 k_star25(SweepArgs a) {
     constexpr int LX = TX / 4;           // lanes per tile row
-    constexpr int NT = LX * TY;          // threads per block
+    constexpr int NT = LX * (TY / RY);   // threads per block
     constexpr int LC = LX + 2;           // LDS chunks per row (incl. x halo)
     constexpr int LR = TY + 8;           // LDS rows (incl. y halo)
     constexpr int HY = 8 * LX;           // y-halo chunks per plane
     constexpr int HC = HY + 2 * TY;      // all halo chunks per plane
-    __shared__ float4 lds[2][LR][LC];
+    constexpr int HPT = (HC + NT - 1) / NT;
+    static_assert(TY % RY == 0, "RY must divide TY");
+    __shared__ f4v lds[2][LR][LC];
 
     const int lin = xcd_tile(blockIdx.x, gridDim.x);
     const int tix = lin % a.tiles_x;
@@ -86,17 +84,24 @@ k_star25(SweepArgs a) {
 
     const int tid = threadIdx.x;
     const int lx = tid % LX, ly = tid / LX;
-    const int x = x0 + 4 * lx, y = y0 + ly;
+    const int x = x0 + 4 * lx;
+    const int ybase = y0 + ly * RY;       // first of this thread's RY rows
     const int64_t sz = a.sz;
 
-    // Own column: loaded while inside the padded extent (rows < ny+4,
+    // Own columns: loaded while inside the padded extent (rows < ny+4,
     // chunks starting before nx+4); stored only for interior points.
-    const bool ld_ok = (y < a.ny + 4) && (x < a.nx + 4);
-    const bool st_ok = (y < a.ny) && (x < a.nx);
-    const int64_t own = (int64_t)y * a.sy + x;
+    bool ld_ok[RY], st_ok[RY];
+    int64_t own[RY], vown[RY];
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+        const int y = ybase + j;
+        ld_ok[j] = (y < a.ny + 4) && (x < a.nx + 4);
+        st_ok[j] = (y < a.ny) && (x < a.nx);
+        own[j] = (int64_t)y * a.sy + x;
+        vown[j] = (int64_t)y * a.vsy + x;
+    }
 
     // Halo chunks owned by this thread (HPT per plane at most).
-    constexpr int HPT = (HC + NT - 1) / NT;
     int hrow[HPT], hchk[HPT];
     bool h_ok[HPT];
     int64_t hoff[HPT];
@@ -123,110 +128,136 @@ k_star25(SweepArgs a) {
         hoff[j] = (int64_t)(y0 + dy) * a.sy + (x0 + dx);
     }
 
-    const float4 zero = f4(0.f);
+    const f4v zero = {0.f, 0.f, 0.f, 0.f};
     const float *u = a.u;
 
-    float4 q[9];
+    f4v q[RY][9];
+    f4v nq[RY];
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
-        q[i] = ld_ok ? ld4(u + (int64_t)(zb - 4 + i) * sz + own) : zero;
-    float4 nq = ld_ok ? ld4(u + (int64_t)(zb + 4) * sz + own) : zero;
-    float4 hv[HPT];
+    for (int j = 0; j < RY; ++j) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            q[j][i] = ld_ok[j] ? ld4(u + (int64_t)(zb - 4 + i) * sz + own[j]) : zero;
+        nq[j] = ld_ok[j] ? ld4(u + (int64_t)(zb + 4) * sz + own[j]) : zero;
+    }
+    f4v hv[HPT];
 #pragma unroll
     for (int j = 0; j < HPT; ++j) hv[j] = h_ok[j] ? ld4(u + (int64_t)zb * sz + hoff[j]) : zero;
 
-    float4 pp = zero, vv = zero;
-    const int64_t vown = (int64_t)y * a.vsy + x;
-    if (MODE == MODE_WAVE && st_ok) {
-        pp = ld4(a.prev + (int64_t)zb * sz + own);
-        vv = ld4(a.v + (int64_t)zb * a.vsz + vown);
+    f4v pp[RY], vv[RY];
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+        pp[j] = zero;
+        vv[j] = zero;
+        if (MODE == MODE_WAVE && st_ok[j]) {
+            pp[j] = ld4_nt(a.prev + (int64_t)zb * sz + own[j]);
+            vv[j] = ld4_nt(a.v + (int64_t)zb * a.vsz + vown[j]);
+        }
     }
 
     const StarCoef &c = a.c;
 
     for (int z = zb; z < ze; ++z) {
-        q[8] = nq;
         const int b = z & 1;
-        lds[b][ly + 4][lx + 1] = q[4];
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            q[j][8] = nq[j];
+            lds[b][ly * RY + j + 4][lx + 1] = q[j][4];
+        }
 #pragma unroll
         for (int j = 0; j < HPT; ++j)
             if (tid + j * NT < HC) lds[b][hrow[j]][hchk[j]] = hv[j];
 
-        float4 pp_n = zero, vv_n = zero;
+        f4v pp_n[RY], vv_n[RY];
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            pp_n[j] = zero;
+            vv_n[j] = zero;
+        }
         if (z + 1 < ze) {
-            nq = ld_ok ? ld4(u + (int64_t)(z + 5) * sz + own) : zero;
+#pragma unroll
+            for (int j = 0; j < RY; ++j)
+                nq[j] = ld_ok[j] ? ld4(u + (int64_t)(z + 5) * sz + own[j]) : zero;
 #pragma unroll
             for (int j = 0; j < HPT; ++j)
                 hv[j] = h_ok[j] ? ld4(u + (int64_t)(z + 1) * sz + hoff[j]) : zero;
-            if (MODE == MODE_WAVE && st_ok) {
-                pp_n = ld4(a.prev + (int64_t)(z + 1) * sz + own);
-                vv_n = ld4(a.v + (int64_t)(z + 1) * a.vsz + vown);
+            if (MODE == MODE_WAVE) {
+#pragma unroll
+                for (int j = 0; j < RY; ++j)
+                    if (st_ok[j]) {
+                        pp_n[j] = ld4_nt(a.prev + (int64_t)(z + 1) * sz + own[j]);
+                        vv_n[j] = ld4_nt(a.v + (int64_t)(z + 1) * a.vsz + vown[j]);
+                    }
             }
         }
 
         lds_barrier();
 
-        const float4 ctr = q[4];
-        float4 acc = make_float4(c.c0 * ctr.x, c.c0 * ctr.y, c.c0 * ctr.z, c.c0 * ctr.w);
+        // y-neighbour rows d = -4 .. RY+3 relative to this thread's first row:
+        // own rows from registers, the rest from LDS.
+        f4v yrow[RY + 8];
 #pragma unroll
-        for (int r = 1; r <= 4; ++r) acc = fma4(c.cz[r - 1], add4(q[4 + r], q[4 - r]), acc);
-#pragma unroll
-        for (int r = 1; r <= 4; ++r)
-            acc = fma4(c.cy[r - 1], add4(lds[b][ly + 4 + r][lx + 1], lds[b][ly + 4 - r][lx + 1]), acc);
-        {
-            const float4 L = lds[b][ly + 4][lx], R = lds[b][ly + 4][lx + 2];
-            const float w[12] = {L.x, L.y, L.z, L.w, ctr.x, ctr.y, ctr.z, ctr.w,
-                                 R.x, R.y, R.z, R.w};
-            float o[4] = {acc.x, acc.y, acc.z, acc.w};
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int r = 1; r <= 4; ++r)
-                    o[i] = fmaf(c.cx[r - 1], w[4 + i + r] + w[4 + i - r], o[i]);
-            acc = make_float4(o[0], o[1], o[2], o[3]);
-        }
+        for (int d = -4; d < RY + 4; ++d)
+            yrow[d + 4] = (d >= 0 && d < RY) ? q[d][4] : lds[b][ly * RY + d + 4][lx + 1];
 
-        float4 res;
-        if (MODE == MODE_WAVE) {
-            const float ms = a.m_scale;
-            float4 m = make_float4(vv.x * vv.x * ms, vv.y * vv.y * ms, vv.z * vv.z * ms,
-                                   vv.w * vv.w * ms);
-            res.x = fmaf(m.x, acc.x, 2.f * ctr.x - pp.x);
-            res.y = fmaf(m.y, acc.y, 2.f * ctr.y - pp.y);
-            res.z = fmaf(m.z, acc.z, 2.f * ctr.z - pp.z);
-            res.w = fmaf(m.w, acc.w, 2.f * ctr.w - pp.w);
-            for (int s = 0; s < a.src.n; ++s) {
-                if (a.src.z[s] == z && a.src.y[s] == y) {
-                    const int d = a.src.x[s] - x;
-                    if (d >= 0 && d < 4) {
-                        const float vs = d == 0 ? vv.x : d == 1 ? vv.y : d == 2 ? vv.z : vv.w;
-                        const float inj = a.src.dt2 * (vs * vs) * a.src.amp[s];
-                        if (d == 0) res.x += inj;
-                        else if (d == 1) res.y += inj;
-                        else if (d == 2) res.z += inj;
-                        else res.w += inj;
-                    }
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            const f4v ctr = q[j][4];
+            f4v acc = c.c0 * ctr;
+#pragma unroll
+            for (int r = 1; r <= 4; ++r) acc += c.cz[r - 1] * (q[j][4 + r] + q[j][4 - r]);
+#pragma unroll
+            for (int r = 1; r <= 4; ++r) acc += c.cy[r - 1] * (yrow[j + 4 + r] + yrow[j + 4 - r]);
+            {
+                const f4v L = lds[b][ly * RY + j + 4][lx], R = lds[b][ly * RY + j + 4][lx + 2];
+                const float w[12] = {L.x, L.y, L.z, L.w, ctr.x, ctr.y, ctr.z, ctr.w,
+                                     R.x, R.y, R.z, R.w};
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    float o = acc[i];
+#pragma unroll
+                    for (int r = 1; r <= 4; ++r) o = fmaf(c.cx[r - 1], w[4 + i + r] + w[4 + i - r], o);
+                    acc[i] = o;
                 }
             }
-        } else {
-            res = acc;
-        }
 
-        if (st_ok) {
-            float *o = a.out + (int64_t)z * sz + own;
-            if (x + 4 <= a.nx) {
-                st4(o, res);
+            f4v res;
+            if (MODE == MODE_WAVE) {
+                const f4v m = vv[j] * vv[j] * a.m_scale;
+                res = m * acc + (2.f * ctr - pp[j]);
+                const int y = ybase + j;
+                for (int s = 0; s < a.src.n; ++s) {
+                    if (a.src.z[s] == z && a.src.y[s] == y) {
+                        const int d = a.src.x[s] - x;
+                        if (d >= 0 && d < 4) {
+                            const float vs = vv[j][d];
+                            res[d] += a.src.dt2 * (vs * vs) * a.src.amp[s];
+                        }
+                    }
+                }
             } else {
-                o[0] = res.x;
-                if (x + 1 < a.nx) o[1] = res.y;
-                if (x + 2 < a.nx) o[2] = res.z;
+                res = acc;
+            }
+
+            if (st_ok[j]) {
+                float *o = a.out + (int64_t)z * sz + own[j];
+                if (x + 4 <= a.nx) {
+                    st4_nt(o, res);
+                } else {
+                    o[0] = res.x;
+                    if (x + 1 < a.nx) o[1] = res.y;
+                    if (x + 2 < a.nx) o[2] = res.z;
+                }
             }
         }
 
 #pragma unroll
-        for (int i = 0; i < 8; ++i) q[i] = q[i + 1];
-        pp = pp_n;
-        vv = vv_n;
+        for (int j = 0; j < RY; ++j) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) q[j][i] = q[j][i + 1];
+            pp[j] = pp_n[j];
+            vv[j] = vv_n[j];
+        }
     }
 }
 
@@ -241,28 +272,36 @@ __global__ void k_record(const float *u, int64_t sy, int64_t sz, int nx, int ny,
     traces[r] = val;
 }
 
-template <int TX, int TY>
+template <int TX, int TY, int RY>
 hipError_t launch_t(int mode, const SweepArgs &a, hipStream_t s) {
     const int nblk = a.tiles_x * a.tiles_y * a.nzc;
-    const dim3 grid(nblk), block((TX / 4) * TY);
+    const dim3 grid(nblk), block((TX / 4) * (TY / RY));
     if (mode == MODE_WAVE)
-        hipLaunchKernelGGL((k_star25<TX, TY, MODE_WAVE>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_star25<TX, TY, RY, MODE_WAVE>), grid, block, 0, s, a);
     else
-        hipLaunchKernelGGL((k_star25<TX, TY, MODE_APPLY>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_star25<TX, TY, RY, MODE_APPLY>), grid, block, 0, s, a);
     return hipGetLastError();
 }
 
 }  // namespace
 
 TileCfg choose_tiles(int nx, int ny, int nz) {
+    // Wide tiles keep the x-halo (one 128-byte line per side per row) and
+    // the y-halo rows small relative to the tile; two rows per thread share
+    // their y-neighbour reads.
     TileCfg t;
-    t.tx = 64;
-    t.ty = 16;
+    if (nx >= 192) {
+        t.tx = 256; t.ty = 16; t.ry = 2;
+    } else if (nx >= 96) {
+        t.tx = 128; t.ty = 16; t.ry = 2;
+    } else {
+        t.tx = 64; t.ty = 16; t.ry = 1;
+    }
     const int tiles = ((nx + t.tx - 1) / t.tx) * ((ny + t.ty - 1) / t.ty);
-    // Enough blocks to give every CU work; split z only when the xy tiling
-    // alone leaves the GPU underfilled (each split re-reads 8 planes of u).
-    const int want = 1024;
-    int chunks = (want + tiles - 1) / tiles;
+    // At least one block per CU; split z only when the xy tiling alone
+    // leaves the GPU underfilled (each split re-reads 8 planes of u).
+    const int want = 256;
+    const int chunks = (want + tiles - 1) / tiles;
     int zc = (nz + chunks - 1) / chunks;
     if (zc < 32) zc = 32;
     if (zc > nz) zc = nz;
@@ -271,9 +310,14 @@ TileCfg choose_tiles(int nx, int ny, int nz) {
 }
 
 hipError_t launch_sweep(int mode, const TileCfg &t, const SweepArgs &a, hipStream_t s) {
-    if (t.tx == 64 && t.ty == 16) return launch_t<64, 16>(mode, a, s);
-    if (t.tx == 64 && t.ty == 8) return launch_t<64, 8>(mode, a, s);
-    if (t.tx == 128 && t.ty == 8) return launch_t<128, 8>(mode, a, s);
+    if (t.tx == 64 && t.ty == 16 && t.ry == 1) return launch_t<64, 16, 1>(mode, a, s);
+    if (t.tx == 128 && t.ty == 16 && t.ry == 2) return launch_t<128, 16, 2>(mode, a, s);
+    if (t.tx == 128 && t.ty == 32 && t.ry == 2) return launch_t<128, 32, 2>(mode, a, s);
+    if (t.tx == 256 && t.ty == 16 && t.ry == 2) return launch_t<256, 16, 2>(mode, a, s);
+    if (t.tx == 256 && t.ty == 16 && t.ry == 4) return launch_t<256, 16, 4>(mode, a, s);
+    if (t.tx == 64 && t.ty == 32 && t.ry == 2) return launch_t<64, 32, 2>(mode, a, s);
+    if (t.tx == 256 && t.ty == 8 && t.ry == 2) return launch_t<256, 8, 2>(mode, a, s);
+    if (t.tx == 256 && t.ty == 8 && t.ry == 1) return launch_t<256, 8, 1>(mode, a, s);
     return hipErrorInvalidValue;
 }
 

@@ -238,3 +238,42 @@ def test_apply_full_size_sampled_parity(gpu_lib):
     e = errors(got, ref)
     print("1024x1024x512 sampled apply vs oracle:", e)
     assert e["rel_l2"] <= TOL_SWEEP
+
+
+TILE_CONFIGS = ["64x16x1", "128x16x2", "128x32x2", "256x16x2", "256x16x4", "64x32x2",
+                "256x8x2", "256x8x1", "64x16x1x7", "128x16x2x33", "256x16x2x40"]
+
+
+@pytest.mark.parametrize("tile", TILE_CONFIGS)
+def test_every_tile_config_single_step(gpu_lib, tile, monkeypatch):
+    # Each compiled launch configuration (SP_TILE=TXxTYxRY[xZCHUNK]) against
+    # the oracle: one leapfrog step from a random state with a source, on a
+    # ragged grid that spans several tiles in x and y and several z-chunks.
+    from paper_2309_04671_amd import fields
+    lib = _lib()
+    monkeypatch.setenv("SP_TILE", tile)
+    nx, ny, nz = 301, 45, 70
+    g, v, vf = _wave_setup(nx, ny, nz, 2)
+    dx = 10.0
+    dt = synth.cfl_dt(v, dx)
+    co = synth.random_coeffs(4)
+    prev = synth.uniform_field((nz, ny, nx), 17)
+    cur = synth.uniform_field((nz, ny, nx), 18)
+    P = fields.Field(g).set_interior(prev)
+    C = fields.Field(g).set_interior(cur)
+    src_xyz = np.array([[150, 22, 35], [300, 44, 69]], np.int32)
+    amp = torch.tensor([[2.0e4, -1.0e4]], dtype=torch.float32, device="cuda")
+    st = lib.sp_wave_state(C.ptr, P.ptr, None, 0)
+    lib.sp_wave_step(g, lib.coeffs(co), dt, dx, g, vf.ptr, st, 1,
+                     src=lib.make_sources(src_xyz, amp.data_ptr(), 2))
+    torch.cuda.synchronize()
+    r = oracle.wave_run(co, v, dt, dx, 1, src=src_xyz, amp=amp.cpu().double().numpy(),
+                        prev=oracle.padded(prev), cur=oracle.padded(cur))
+    e = errors(P.get_interior(), oracle.interior(r["cur"]))
+    assert e["rel_l2"] <= TOL_SWEEP, (tile, e)
+    # apply in the same configuration
+    U, W = fields.Field(g).set_interior(cur), fields.Field(g)
+    assert lib.sp_stencil_apply(g, lib.coeffs(co), 1, U.ptr, W.ptr) == 1
+    torch.cuda.synchronize()
+    e = errors(W.get_interior(), oracle.laplacian(oracle.padded(cur), co))
+    assert e["rel_l2"] <= TOL_SWEEP, (tile, e)
