@@ -104,10 +104,23 @@ int sp_stencil_apply(const sp_grid *g, const sp_coeffs *c, int sweeps,
 /*
  * Wavefield state of the leapfrog.  cur = u^n, prev = u^{n-1}; a step writes
  * u^{n+1} over prev and swaps the two pointers, so on return cur is the
- * newest state.  For FP16/BF16 grids `meta` points at sp_wave_meta_bytes()
- * bytes of per-slab records (scales and maxima; zero-filled by the caller
- * before the first step of zero fields); it must be NULL for FP32.
- * `step` counts steps taken; it indexes the source amplitudes.
+ * newest state.  `step` (= n) counts steps taken; it indexes the source
+ * amplitudes and the FP16/BF16 records.  `meta` must be NULL for FP32.
+ *
+ * FP16/BF16 storage: a stored value q of a point in z-slab k (planes
+ * 16k .. 16k+15) stands for q * s_k, s_k a power of two per field and slab.
+ * `meta` points at sp_wave_meta_bytes() DEVICE bytes holding 4 slots; field
+ * u^j uses slot j mod 4 (u^{-1}: slot 3).  Slot layout, nslab = ceil(nz/16):
+ *     float    scale[nslab];   s_k
+ *     uint32_t amax[nslab];    IEEE bits of max |q| * s_k over slab k
+ * Zero-fill the block before the first step from zero fields; to start from
+ * non-zero fields, fill slots 0 (u^0) and 3 (u^{-1}) consistently.  Step n
+ * chooses s_k of u^{n+1} before computing it:
+ *     B_k = 8 max(amax(u^n) slabs k-1..k+1, amax(u^{n-1}) slab k)
+ *           + sum over sources in slab k of |dt^2 v^2 amp|  (FP32),
+ *     s_k = 2^(ceil(log2 B_k) - 15)  (1 if B_k = 0),
+ * which keeps |q| <= 2^15 inside the stability limit; values are rounded to
+ * nearest even.  Halo planes are decoded with the nearest slab's scale.
  */
 typedef struct {
     void *cur;

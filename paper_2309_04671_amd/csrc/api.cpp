@@ -65,7 +65,10 @@ void fill_tiling(sp::SweepArgs &a, const sp::TileCfg &t) {
     a.nzc = (a.nz + t.zchunk - 1) / t.zchunk;
 }
 
-sp::TileCfg tiles_for(const sp_grid *g) {
+// Launch configuration for a grid; SP_TILE=TXxTYxRY[xZC] overrides it for
+// tuning.  Returns false (with the error set) for a configuration that is
+// not compiled in.
+bool tiles_for(const sp_grid *g, sp::TileCfg *out, const char *who) {
     sp::TileCfg t = sp::choose_tiles(g->nx, g->ny, g->nz);
     // Optional override for tuning: SP_TILE=TXxTYxRY[xZC]
     if (const char *e = std::getenv("SP_TILE")) {
@@ -78,7 +81,12 @@ sp::TileCfg tiles_for(const sp_grid *g) {
         }
         if (n == 4 && zc > 0) t.zchunk = std::min(zc, g->nz);
     }
-    return t;
+    if (!sp::tile_supported(t)) {
+        fail(SP_EINVAL, "%s: tile configuration %dx%dx%d is not compiled in", who, t.tx, t.ty, t.ry);
+        return false;
+    }
+    *out = t;
+    return true;
 }
 
 }  // namespace
@@ -138,7 +146,8 @@ int sp_stencil_apply(const sp_grid *g, const sp_coeffs *c, int sweeps, void *u, 
     a.sy = g->pitch_x;
     a.sz = g->pitch_x * g->pitch_y;
     a.c = to_f32(c);
-    const sp::TileCfg t = tiles_for(g);
+    sp::TileCfg t;
+    if (!tiles_for(g, &t, "sp_stencil_apply")) return SP_EINVAL;
     fill_tiling(a, t);
     float *bufs[2] = {static_cast<float *>(u) + g->origin, static_cast<float *>(v) + g->origin};
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -146,7 +155,7 @@ int sp_stencil_apply(const sp_grid *g, const sp_coeffs *c, int sweeps, void *u, 
     for (int k = 0; k < sweeps; ++k) {
         a.u = bufs[in];
         a.out = bufs[1 - in];
-        hipError_t err = sp::launch_sweep(sp::MODE_APPLY, t, a, s);
+        hipError_t err = sp::launch_sweep(sp::MODE_APPLY, SP_F32, t, a, s);
         if (err != hipSuccess)
             return fail(SP_EDEVICE, "sp_stencil_apply: launch failed: %s", hipGetErrorString(err));
         in = 1 - in;
@@ -158,7 +167,7 @@ int sp_stencil_apply(const sp_grid *g, const sp_coeffs *c, int sweeps, void *u, 
 int64_t sp_wave_meta_bytes(const sp_grid *g) {
     if (!g || g->dtype == SP_F32) return 0;
     const int64_t nslab = (g->nz + SP_SLAB - 1) / SP_SLAB;
-    return 3 * 2 * nslab * (int64_t)sizeof(float);
+    return 4 * 2 * nslab * (int64_t)sizeof(float);
 }
 
 int sp_wave_step(const sp_grid *g, const sp_coeffs *c, double dt, double dx, const sp_grid *gv,
@@ -168,9 +177,10 @@ int sp_wave_step(const sp_grid *g, const sp_coeffs *c, double dt, double dx, con
     if (int e = check_grid(gv, "sp_wave_step(v)")) return e;
     if (gv->dtype != SP_F32 || gv->nx != g->nx || gv->ny != g->ny || gv->nz != g->nz)
         return fail(SP_EINVAL, "sp_wave_step: v must be an FP32 grid of the same shape");
-    if (g->dtype != SP_F32) return fail(SP_EUNSUPPORTED, "sp_wave_step: storage dtype %d not built", g->dtype);
     if (!c || !v || !st || !st->cur || !st->prev) return fail(SP_EINVAL, "sp_wave_step: NULL argument");
-    if (st->meta) return fail(SP_EINVAL, "sp_wave_step: meta must be NULL for FP32 grids");
+    if (g->dtype == SP_F32 && st->meta) return fail(SP_EINVAL, "sp_wave_step: meta must be NULL for FP32 grids");
+    if (g->dtype != SP_F32 && (!st->meta || !aligned16(st->meta)))
+        return fail(SP_EINVAL, "sp_wave_step: FP16/BF16 grids need a 16-byte aligned meta block");
     if (nsteps < 0) return fail(SP_EINVAL, "sp_wave_step: nsteps < 0");
     if (!(dt > 0) || !(dx > 0)) return fail(SP_EINVAL, "sp_wave_step: dt and dx must be > 0");
     if (!aligned16(st->cur) || !aligned16(st->prev) || !aligned16(v))
@@ -219,20 +229,41 @@ int sp_wave_step(const sp_grid *g, const sp_coeffs *c, double dt, double dx, con
         a.src.y[s] = src->xyz[s][1];
         a.src.z[s] = src->xyz[s][2];
     }
-    const sp::TileCfg t = tiles_for(g);
+    sp::TileCfg t;
+    if (!tiles_for(g, &t, "sp_wave_step")) return SP_EINVAL;
     fill_tiling(a, t);
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t step0 = st->step;
+    const int64_t eb = g->elem_bytes;
+    const int nslab = (g->nz + SP_SLAB - 1) / SP_SLAB;
+    float *meta = static_cast<float *>(st->meta);
+    auto slot_s = [&](int64_t k) { return meta + ((k % 4 + 4) % 4) * 2 * nslab; };
+    auto slot_a = [&](int64_t k) {
+        return reinterpret_cast<uint32_t *>(meta + ((k % 4 + 4) % 4) * 2 * nslab + nslab);
+    };
     for (int k = 0; k < nsteps; ++k) {
-        float *cur = static_cast<float *>(st->cur) + g->origin;
-        float *prev = static_cast<float *>(st->prev) + g->origin;
+        char *cur = static_cast<char *>(st->cur) + g->origin * eb;
+        char *prev = static_cast<char *>(st->prev) + g->origin * eb;
         a.u = cur;
         a.prev = prev;
         a.out = prev;
+        const int64_t n = st->step;
+        if (meta) {
+            a.meta.nslab = nslab;
+            a.meta.s_u = slot_s(n);
+            a.meta.a_u = slot_a(n);
+            a.meta.s_prev = slot_s(n - 1);
+            a.meta.a_prev = slot_a(n - 1);
+            a.meta.s_out = slot_s(n + 1);
+            a.meta.a_out = slot_a(n + 1);
+            a.meta.s_clear = slot_s(n + 2);
+            a.meta.a_clear = slot_a(n + 2);
+        }
         if (nsrc > 0) a.src.amp = src->amp + st->step * src->amp_stride;
-        hipError_t err = sp::launch_sweep(sp::MODE_WAVE, t, a, s);
+        hipError_t err = sp::launch_sweep(sp::MODE_WAVE, g->dtype, t, a, s);
         if (err == hipSuccess && nrec > 0)
-            err = sp::launch_record(prev, a.sy, a.sz, g->nx, g->ny, g->nz, rec->xyz, nrec,
+            err = sp::launch_record(g->dtype, prev, meta ? slot_s(n + 1) : nullptr, a.sy, a.sz,
+                                    g->nx, g->ny, g->nz, rec->xyz, nrec,
                                     rec->traces + (st->step - step0) * rec->trace_stride, s);
         if (err != hipSuccess)
             return fail(SP_EDEVICE, "sp_wave_step: launch failed at step %lld: %s",

@@ -28,18 +28,37 @@ struct SrcList {
     float dt2;          // dt^2 (injection = dt^2 v^2 amp)
 };
 
-// Arguments of one sweep of the streaming star kernel (FP32 storage).
+// Per-slab scale records of FP16/BF16 fields (SP_SLAB planes per slab).
+// Slot layout in the caller's meta block: 4 slots, each holding
+// float scale[nslab] followed by uint32 amax[nslab] (IEEE bits of a
+// non-negative float, so integer max is float max).  Field u^k uses slot
+// k mod 4.
+struct SlabMeta {
+    const float *s_u;        // scales of u^n
+    const float *s_prev;     // scales of u^{n-1}
+    const uint32_t *a_u;     // maxima of |u^n|
+    const uint32_t *a_prev;  // maxima of |u^{n-1}|
+    float *s_out;            // scales of u^{n+1} (written here)
+    uint32_t *a_out;         // maxima of |u^{n+1}| (atomic max; zero on entry)
+    float *s_clear;          // slot of u^{n+2}: cleared by block 0
+    uint32_t *a_clear;
+    int nslab;
+};
+
+// Arguments of one sweep of the streaming star kernel.  Field pointers are
+// at the interior origin and typed by the storage type of the launch.
 struct SweepArgs {
-    const float *u;      // input field at interior origin
-    const float *prev;   // u^{n-1} at origin (MODE_WAVE; may alias out)
+    const void *u;       // input field
+    const void *prev;    // u^{n-1} (MODE_WAVE; may alias out)
     const float *v;      // velocity at its origin (MODE_WAVE)
-    float *out;          // output at origin
+    void *out;           // output field
     int nx, ny, nz;
     int64_t sy, sz;      // row / plane strides of u, prev, out (elements)
     int64_t vsy, vsz;    // row / plane strides of v
     float m_scale;       // (dt / dx)^2, so m = v^2 m_scale
     StarCoef c;
     SrcList src;
+    SlabMeta meta;       // FP16/BF16 storage only
     int tiles_x, tiles_y, zchunk, nzc;
 };
 
@@ -51,8 +70,11 @@ struct TileCfg {
 };
 
 TileCfg choose_tiles(int nx, int ny, int nz);
-hipError_t launch_sweep(int mode, const TileCfg &t, const SweepArgs &a, hipStream_t s);
-hipError_t launch_record(const float *u, int64_t sy, int64_t sz, int nx, int ny, int nz,
-                         const int32_t *xyz, int n, float *traces, hipStream_t s);
+bool tile_supported(const TileCfg &t);
+hipError_t launch_sweep(int mode, int dtype, const TileCfg &t, const SweepArgs &a, hipStream_t s);
+// Record u at receiver points (decoding with per-slab scales if `scale`).
+hipError_t launch_record(int dtype, const void *u, const float *scale, int64_t sy, int64_t sz,
+                         int nx, int ny, int nz, const int32_t *xyz, int n, float *traces,
+                         hipStream_t s);
 
 }  // namespace sp

@@ -2,23 +2,31 @@
 //
 // One kernel computes one sweep of the star of the paper's Eq. 3 over the
 // interior, optionally fused with the leapfrog update of Eq. 2 and the point
-// source term of Algorithm 1.
+// source term of Algorithm 1.  Wavefields may be stored in FP32, FP16 or
+// BF16; all arithmetic is FP32.
 //
-// Design (MI355X-first, HBM-bound: ~41 FLOP per 16 B moved):
+// Design (MI355X-first, HBM-bound: ~41 FLOP per 16 B moved in FP32):
 //  * A workgroup owns an xy tile of TX x TY points and streams along z over a
 //    chunk of planes (2.5D blocking).  Each lane owns 4 consecutive x points
-//    of one row and moves them with one 16-byte load/store (x-contiguous,
-//    128-byte aligned rows, so a wave's row segments fill whole cache lines).
-//  * z-neighbours come from a 9-deep register queue per lane (planes z-4 ..
+//    of RY adjacent rows and moves each row's 4 values with one vector
+//    load/store (x-contiguous, 128-byte aligned rows).
+//  * z-neighbours come from a 9-deep register queue per row (planes z-4 ..
 //    z+4); each plane of u is fetched from HBM once per tile.
 //  * x/y-neighbours come from an LDS copy of plane z: the tile plus a 4-wide
 //    frame of halo chunks (star shape: no corners), double-buffered so one
-//    barrier per plane suffices.
-//  * All loads for plane z+1 (queue head, halo frame, u^{n-1}, v) are issued
+//    barrier per plane suffices; rows owned by the thread itself are taken
+//    from registers.
+//  * Loads for plane z+1 (queue head, halo frame, u^{n-1}, v) are issued
 //    before the barrier of plane z, so HBM latency overlaps the compute.
+//    u^{n-1}, v and the output are touched once: non-temporal accesses keep
+//    them from displacing u lines that neighbouring tiles re-read from L2.
 //  * Tiles are mapped to blocks so that consecutive tiles run on the same XCD
 //    (workgroups are dealt round-robin over the 8 XCDs, each with its own L2):
-//    y-neighbouring tiles then share halo rows through that XCD's L2.
+//    neighbouring tiles then share halo lines through that XCD's L2.
+//  * FP16/BF16 storage: value = stored * 2^e per 16-plane slab.  Each step
+//    chooses the output slab exponent a priori from the maxima of its inputs
+//    (so the stored magnitude stays <= 2^15), and reduces the output maxima
+//    for the next step with one atomic max per wave and slab.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -29,18 +37,69 @@ namespace sp {
 namespace {
 
 typedef float f4v __attribute__((ext_vector_type(4)));
+typedef _Float16 h4v __attribute__((ext_vector_type(4)));
+typedef uint16_t u4v __attribute__((ext_vector_type(4)));
+typedef __bf16 b4v __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ f4v ld4(const float *p) {
-    return *reinterpret_cast<const f4v *>(p);
-}
+// Storage type <-> FP32.  dec(raw, s) = stored * s; enc(v, inv) stores
+// round-to-nearest-even(v * inv), inv = 1/s (a power of two, so exact).
+template <typename T> struct Io;
 
-// Streamed-once data: non-temporal hint keeps it from displacing reused lines.
+template <> struct Io<float> {
+    typedef f4v raw;
+    static constexpr bool scaled = false;
+    __device__ static raw ld(const float *p) { return *reinterpret_cast<const f4v *>(p); }
+    __device__ static raw ld_nt(const float *p) {
+        return __builtin_nontemporal_load(reinterpret_cast<const f4v *>(p));
+    }
+    __device__ static f4v dec(raw r, float) { return r; }
+    __device__ static raw enc(f4v v, float) { return v; }
+    __device__ static void st_nt(float *p, raw r) {
+        __builtin_nontemporal_store(r, reinterpret_cast<f4v *>(p));
+    }
+    __device__ static float dec1(float r, float) { return r; }
+    __device__ static f4v mag(raw r) { return __builtin_elementwise_abs(r); }
+};
+
+template <> struct Io<_Float16> {
+    typedef h4v raw;
+    static constexpr bool scaled = true;
+    __device__ static raw ld(const _Float16 *p) { return *reinterpret_cast<const h4v *>(p); }
+    __device__ static raw ld_nt(const _Float16 *p) {
+        return __builtin_nontemporal_load(reinterpret_cast<const h4v *>(p));
+    }
+    __device__ static f4v dec(raw r, float s) { return __builtin_convertvector(r, f4v) * s; }
+    __device__ static raw enc(f4v v, float inv) { return __builtin_convertvector(v * inv, h4v); }
+    __device__ static void st_nt(_Float16 *p, raw r) {
+        __builtin_nontemporal_store(r, reinterpret_cast<h4v *>(p));
+    }
+    __device__ static float dec1(_Float16 r, float s) { return (float)r * s; }
+    __device__ static f4v mag(raw r) {
+        return __builtin_elementwise_abs(__builtin_convertvector(r, f4v));
+    }
+};
+
+template <> struct Io<__bf16> {
+    typedef b4v raw;
+    static constexpr bool scaled = true;
+    __device__ static raw ld(const __bf16 *p) { return *reinterpret_cast<const b4v *>(p); }
+    __device__ static raw ld_nt(const __bf16 *p) {
+        return __builtin_bit_cast(
+            b4v, __builtin_nontemporal_load(reinterpret_cast<const u4v *>(p)));
+    }
+    __device__ static f4v dec(raw r, float s) { return __builtin_convertvector(r, f4v) * s; }
+    __device__ static raw enc(f4v v, float inv) { return __builtin_convertvector(v * inv, b4v); }
+    __device__ static void st_nt(__bf16 *p, raw r) {
+        __builtin_nontemporal_store(__builtin_bit_cast(u4v, r), reinterpret_cast<u4v *>(p));
+    }
+    __device__ static float dec1(__bf16 r, float s) { return (float)r * s; }
+    __device__ static f4v mag(raw r) {
+        return __builtin_elementwise_abs(__builtin_convertvector(r, f4v));
+    }
+};
+
 __device__ __forceinline__ f4v ld4_nt(const float *p) {
     return __builtin_nontemporal_load(reinterpret_cast<const f4v *>(p));
-}
-
-__device__ __forceinline__ void st4_nt(float *p, f4v v) {
-    __builtin_nontemporal_store(v, reinterpret_cast<f4v *>(p));
 }
 
 // Barrier that orders LDS traffic only; pending global loads stay in flight.
@@ -57,12 +116,47 @@ __device__ __forceinline__ int xcd_tile(int bid, int n) {
     return xcd * q + (xcd < r ? xcd : r) + loc;
 }
 
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// Scale of plane z of a field with per-slab scales (halo planes use the
+// nearest slab).
+__device__ __forceinline__ float plane_scale(const float *s, int z, int nslab) {
+    return s[clampi(z >> 4, 0, nslab - 1)];
+}
+
+// Slab exponent rule: B = 8 max(|u^n| on slabs k-1..k+1, |u^{n-1}| on slab k)
+// + sum of |injections| in slab k; scale = 2^(ceil(log2 B) - 15), or 1 when
+// B = 0.  Since |u^{n+1}| <= (3 + m sum|c|) max|inputs| < 8 max|inputs| for
+// any Courant number inside the stability limit, |stored| <= 2^15.
+__device__ float slab_scale(const SweepArgs &a, int k) {
+    const SlabMeta &m = a.meta;
+    float M = __uint_as_float(m.a_u[k]);
+    if (k > 0) M = fmaxf(M, __uint_as_float(m.a_u[k - 1]));
+    if (k + 1 < m.nslab) M = fmaxf(M, __uint_as_float(m.a_u[k + 1]));
+    M = fmaxf(M, __uint_as_float(m.a_prev[k]));
+    float B = 8.f * M;
+    for (int s = 0; s < a.src.n; ++s) {
+        if ((a.src.z[s] >> 4) == k) {
+            const float vs = a.v[(int64_t)a.src.z[s] * a.vsz + (int64_t)a.src.y[s] * a.vsy + a.src.x[s]];
+            B += fabsf(a.src.dt2 * (vs * vs) * a.src.amp[s]);
+        }
+    }
+    if (!(B > 0.f)) return 1.f;
+    int E;
+    const float mant = frexpf(B, &E);          // B = mant * 2^E, mant in [0.5, 1)
+    int e = (mant == 0.5f ? E - 1 : E) - 15;   // ceil(log2 B) - 15
+    e = clampi(e, -110, 110);
+    return ldexpf(1.f, e);
+}
+
 // One sweep over the block's tile and z-chunk.
 //   TX: tile width in points (4 per lane), TY: tile height in rows,
-//   RY: adjacent rows per thread (register blocking in y).
-template <int TX, int TY, int RY, int MODE>
+//   RY: adjacent rows per thread (register blocking in y), T: storage type.
+template <int TX, int TY, int RY, int MODE, typename T>
 __global__ void __launch_bounds__((TX / 4) * (TY / RY))
 k_star25(SweepArgs a) {
+    typedef Io<T> IO;
+    typedef typename IO::raw raw;
     constexpr int LX = TX / 4;           // lanes per tile row
     constexpr int NT = LX * (TY / RY);   // threads per block
     constexpr int LC = LX + 2;           // LDS chunks per row (incl. x halo)
@@ -71,6 +165,7 @@ k_star25(SweepArgs a) {
     constexpr int HC = HY + 2 * TY;      // all halo chunks per plane
     constexpr int HPT = (HC + NT - 1) / NT;
     static_assert(TY % RY == 0, "RY must divide TY");
+    static_assert(MODE == MODE_WAVE || !IO::scaled, "apply is FP32 only");
     __shared__ f4v lds[2][LR][LC];
 
     const int lin = xcd_tile(blockIdx.x, gridDim.x);
@@ -87,6 +182,19 @@ k_star25(SweepArgs a) {
     const int x = x0 + 4 * lx;
     const int ybase = y0 + ly * RY;       // first of this thread's RY rows
     const int64_t sz = a.sz;
+    const T *u = static_cast<const T *>(a.u);
+    const T *uprev = static_cast<const T *>(a.prev);
+    T *out = static_cast<T *>(a.out);
+    const int nslab = a.meta.nslab;
+
+    if constexpr (IO::scaled) {
+        // retire the records of u^{n-2}: that slot receives u^{n+2} next step
+        if (lin == 0)
+            for (int i = tid; i < nslab; i += NT) {
+                a.meta.s_clear[i] = 0.f;
+                a.meta.a_clear[i] = 0u;
+            }
+    }
 
     // Own columns: loaded while inside the padded extent (rows < ny+4,
     // chunks starting before nx+4); stored only for interior points.
@@ -129,63 +237,81 @@ k_star25(SweepArgs a) {
     }
 
     const f4v zero = {0.f, 0.f, 0.f, 0.f};
-    const float *u = a.u;
+    const raw rzero = IO::enc(zero, 1.f);
+
+    auto su = [&](int zz) { return IO::scaled ? plane_scale(a.meta.s_u, zz, nslab) : 1.f; };
+    auto sprev = [&](int zz) { return IO::scaled ? plane_scale(a.meta.s_prev, zz, nslab) : 1.f; };
 
     f4v q[RY][9];
-    f4v nq[RY];
+    raw nq[RY];
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i)
-            q[j][i] = ld_ok[j] ? ld4(u + (int64_t)(zb - 4 + i) * sz + own[j]) : zero;
-        nq[j] = ld_ok[j] ? ld4(u + (int64_t)(zb + 4) * sz + own[j]) : zero;
+        for (int i = 0; i < 8; ++i) {
+            const int zz = zb - 4 + i;
+            q[j][i] = ld_ok[j] ? IO::dec(IO::ld(u + (int64_t)zz * sz + own[j]), su(zz)) : zero;
+        }
+        nq[j] = ld_ok[j] ? IO::ld(u + (int64_t)(zb + 4) * sz + own[j]) : rzero;
     }
-    f4v hv[HPT];
+    raw hv[HPT];
 #pragma unroll
-    for (int j = 0; j < HPT; ++j) hv[j] = h_ok[j] ? ld4(u + (int64_t)zb * sz + hoff[j]) : zero;
+    for (int j = 0; j < HPT; ++j) hv[j] = h_ok[j] ? IO::ld(u + (int64_t)zb * sz + hoff[j]) : rzero;
 
-    f4v pp[RY], vv[RY];
+    raw pp[RY];
+    f4v vv[RY];
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
-        pp[j] = zero;
+        pp[j] = rzero;
         vv[j] = zero;
         if (MODE == MODE_WAVE && st_ok[j]) {
-            pp[j] = ld4_nt(a.prev + (int64_t)zb * sz + own[j]);
+            pp[j] = IO::ld_nt(uprev + (int64_t)zb * sz + own[j]);
             vv[j] = ld4_nt(a.v + (int64_t)zb * a.vsz + vown[j]);
         }
     }
 
     const StarCoef &c = a.c;
+    float s_out = 1.f, inv_out = 1.f;     // output scale of the current slab
+    float tmax = 0.f;                     // running max |stored output| in the slab
 
     for (int z = zb; z < ze; ++z) {
         const int b = z & 1;
+        if constexpr (IO::scaled) {
+            if (z == zb || (z & (SP_SLAB - 1)) == 0) {
+                const int k = z >> 4;
+                s_out = slab_scale(a, k);
+                inv_out = 1.f / s_out;
+                if (lin % (a.tiles_x * a.tiles_y) == 0 && tid == 0) a.meta.s_out[k] = s_out;
+            }
+        }
+        const float s4 = su(z + 4), s0 = su(z);
 #pragma unroll
         for (int j = 0; j < RY; ++j) {
-            q[j][8] = nq[j];
+            q[j][8] = IO::dec(nq[j], s4);
             lds[b][ly * RY + j + 4][lx + 1] = q[j][4];
         }
 #pragma unroll
         for (int j = 0; j < HPT; ++j)
-            if (tid + j * NT < HC) lds[b][hrow[j]][hchk[j]] = hv[j];
+            if (tid + j * NT < HC) lds[b][hrow[j]][hchk[j]] = IO::dec(hv[j], s0);
 
-        f4v pp_n[RY], vv_n[RY];
+        raw pp_n[RY];
+        f4v vv_n[RY];
 #pragma unroll
         for (int j = 0; j < RY; ++j) {
-            pp_n[j] = zero;
+            pp_n[j] = rzero;
             vv_n[j] = zero;
         }
         if (z + 1 < ze) {
 #pragma unroll
             for (int j = 0; j < RY; ++j)
-                nq[j] = ld_ok[j] ? ld4(u + (int64_t)(z + 5) * sz + own[j]) : zero;
+                nq[j] = ld_ok[j] ? IO::ld(u + (int64_t)(z + 5) * sz + own[j]) : rzero;
 #pragma unroll
             for (int j = 0; j < HPT; ++j)
-                hv[j] = h_ok[j] ? ld4(u + (int64_t)(z + 1) * sz + hoff[j]) : zero;
+                hv[j] = h_ok[j] ? IO::ld(u + (int64_t)(z + 1) * sz + hoff[j]) : rzero;
             if (MODE == MODE_WAVE) {
 #pragma unroll
                 for (int j = 0; j < RY; ++j)
                     if (st_ok[j]) {
-                        pp_n[j] = ld4_nt(a.prev + (int64_t)(z + 1) * sz + own[j]);
+                        pp_n[j] = IO::ld_nt(uprev + (int64_t)(z + 1) * sz + own[j]);
                         vv_n[j] = ld4_nt(a.v + (int64_t)(z + 1) * a.vsz + vown[j]);
                     }
             }
@@ -200,6 +326,7 @@ k_star25(SweepArgs a) {
         for (int d = -4; d < RY + 4; ++d)
             yrow[d + 4] = (d >= 0 && d < RY) ? q[d][4] : lds[b][ly * RY + d + 4][lx + 1];
 
+        const float sp0 = sprev(z);
 #pragma unroll
         for (int j = 0; j < RY; ++j) {
             const f4v ctr = q[j][4];
@@ -224,7 +351,7 @@ k_star25(SweepArgs a) {
             f4v res;
             if (MODE == MODE_WAVE) {
                 const f4v m = vv[j] * vv[j] * a.m_scale;
-                res = m * acc + (2.f * ctr - pp[j]);
+                res = m * acc + (2.f * ctr - IO::dec(pp[j], sp0));
                 const int y = ybase + j;
                 for (int s = 0; s < a.src.n; ++s) {
                     if (a.src.z[s] == z && a.src.y[s] == y) {
@@ -240,14 +367,33 @@ k_star25(SweepArgs a) {
             }
 
             if (st_ok[j]) {
-                float *o = a.out + (int64_t)z * sz + own[j];
-                if (x + 4 <= a.nx) {
-                    st4_nt(o, res);
-                } else {
-                    o[0] = res.x;
-                    if (x + 1 < a.nx) o[1] = res.y;
-                    if (x + 2 < a.nx) o[2] = res.z;
+                T *o = out + (int64_t)z * sz + own[j];
+                const raw enc = IO::enc(res, inv_out);
+                if constexpr (IO::scaled) {
+                    const f4v mg = IO::mag(enc);
+                    float mm = mg.x;
+                    if (x + 1 < a.nx) mm = fmaxf(mm, mg.y);   // ragged chunk: interior points only
+                    if (x + 2 < a.nx) mm = fmaxf(mm, mg.z);
+                    if (x + 3 < a.nx) mm = fmaxf(mm, mg.w);
+                    tmax = fmaxf(tmax, mm);
                 }
+                if (x + 4 <= a.nx) {
+                    IO::st_nt(o, enc);
+                } else {
+                    o[0] = enc[0];
+                    if (x + 1 < a.nx) o[1] = enc[1];
+                    if (x + 2 < a.nx) o[2] = enc[2];
+                }
+            }
+        }
+
+        if constexpr (IO::scaled) {
+            if (z + 1 == ze || ((z + 1) & (SP_SLAB - 1)) == 0) {
+                float w = tmax;
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) w = fmaxf(w, __shfl_xor(w, off, 64));
+                if ((tid & 63) == 0) atomicMax(&a.meta.a_out[z >> 4], __float_as_uint(w * s_out));
+                tmax = 0.f;
             }
         }
 
@@ -261,29 +407,50 @@ k_star25(SweepArgs a) {
     }
 }
 
-__global__ void k_record(const float *u, int64_t sy, int64_t sz, int nx, int ny, int nz,
-                         const int32_t *xyz, int n, float *traces) {
+template <typename T>
+__global__ void k_record(const T *u, const float *scale, int64_t sy, int64_t sz, int nx, int ny,
+                         int nz, const int32_t *xyz, int n, float *traces) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
     const int x = xyz[3 * r], y = xyz[3 * r + 1], z = xyz[3 * r + 2];
     float val = 0.f;
-    if (x >= 0 && x < nx && y >= 0 && y < ny && z >= 0 && z < nz)
-        val = u[(int64_t)z * sz + (int64_t)y * sy + x];
+    if (x >= 0 && x < nx && y >= 0 && y < ny && z >= 0 && z < nz) {
+        const float s = scale ? scale[z >> 4] : 1.f;
+        val = Io<T>::dec1(u[(int64_t)z * sz + (int64_t)y * sy + x], s);
+    }
     traces[r] = val;
 }
 
-template <int TX, int TY, int RY>
+template <int TX, int TY, int RY, typename T>
 hipError_t launch_t(int mode, const SweepArgs &a, hipStream_t s) {
     const int nblk = a.tiles_x * a.tiles_y * a.nzc;
     const dim3 grid(nblk), block((TX / 4) * (TY / RY));
-    if (mode == MODE_WAVE)
-        hipLaunchKernelGGL((k_star25<TX, TY, RY, MODE_WAVE>), grid, block, 0, s, a);
-    else
-        hipLaunchKernelGGL((k_star25<TX, TY, RY, MODE_APPLY>), grid, block, 0, s, a);
+    if (mode == MODE_WAVE) {
+        hipLaunchKernelGGL((k_star25<TX, TY, RY, MODE_WAVE, T>), grid, block, 0, s, a);
+    } else {
+        if constexpr (Io<T>::scaled) return hipErrorInvalidValue;
+        else hipLaunchKernelGGL((k_star25<TX, TY, RY, MODE_APPLY, T>), grid, block, 0, s, a);
+    }
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_cfg(int mode, const TileCfg &t, const SweepArgs &a, hipStream_t s) {
+    if (t.tx == 256 && t.ty == 16 && t.ry == 2) return launch_t<256, 16, 2, T>(mode, a, s);
+    if (t.tx == 128 && t.ty == 16 && t.ry == 2) return launch_t<128, 16, 2, T>(mode, a, s);
+    if (t.tx == 64 && t.ty == 16 && t.ry == 1) return launch_t<64, 16, 1, T>(mode, a, s);
+    if (t.tx == 128 && t.ty == 32 && t.ry == 2) return launch_t<128, 32, 2, T>(mode, a, s);
+    if (t.tx == 256 && t.ty == 8 && t.ry == 2) return launch_t<256, 8, 2, T>(mode, a, s);
+    return hipErrorInvalidValue;
+}
+
 }  // namespace
+
+bool tile_supported(const TileCfg &t) {
+    return (t.tx == 256 && t.ty == 16 && t.ry == 2) || (t.tx == 128 && t.ty == 16 && t.ry == 2) ||
+           (t.tx == 64 && t.ty == 16 && t.ry == 1) || (t.tx == 128 && t.ty == 32 && t.ry == 2) ||
+           (t.tx == 256 && t.ty == 8 && t.ry == 2);
+}
 
 TileCfg choose_tiles(int nx, int ny, int nz) {
     // Wide tiles keep the x-halo (one 128-byte line per side per row) and
@@ -309,24 +476,36 @@ TileCfg choose_tiles(int nx, int ny, int nz) {
     return t;
 }
 
-hipError_t launch_sweep(int mode, const TileCfg &t, const SweepArgs &a, hipStream_t s) {
-    if (t.tx == 64 && t.ty == 16 && t.ry == 1) return launch_t<64, 16, 1>(mode, a, s);
-    if (t.tx == 128 && t.ty == 16 && t.ry == 2) return launch_t<128, 16, 2>(mode, a, s);
-    if (t.tx == 128 && t.ty == 32 && t.ry == 2) return launch_t<128, 32, 2>(mode, a, s);
-    if (t.tx == 256 && t.ty == 16 && t.ry == 2) return launch_t<256, 16, 2>(mode, a, s);
-    if (t.tx == 256 && t.ty == 16 && t.ry == 4) return launch_t<256, 16, 4>(mode, a, s);
-    if (t.tx == 64 && t.ty == 32 && t.ry == 2) return launch_t<64, 32, 2>(mode, a, s);
-    if (t.tx == 256 && t.ty == 8 && t.ry == 2) return launch_t<256, 8, 2>(mode, a, s);
-    if (t.tx == 256 && t.ty == 8 && t.ry == 1) return launch_t<256, 8, 1>(mode, a, s);
-    return hipErrorInvalidValue;
+hipError_t launch_sweep(int mode, int dtype, const TileCfg &t, const SweepArgs &a, hipStream_t s) {
+    switch (dtype) {
+        case SP_F32: return launch_cfg<float>(mode, t, a, s);
+        case SP_F16: return launch_cfg<_Float16>(mode, t, a, s);
+        case SP_BF16: return launch_cfg<__bf16>(mode, t, a, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
-hipError_t launch_record(const float *u, int64_t sy, int64_t sz, int nx, int ny, int nz,
-                         const int32_t *xyz, int n, float *traces, hipStream_t s) {
+hipError_t launch_record(int dtype, const void *u, const float *scale, int64_t sy, int64_t sz,
+                         int nx, int ny, int nz, const int32_t *xyz, int n, float *traces,
+                         hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int bs = 256;
-    hipLaunchKernelGGL(k_record, dim3((n + bs - 1) / bs), dim3(bs), 0, s, u, sy, sz, nx, ny, nz,
-                       xyz, n, traces);
+    const dim3 g((n + bs - 1) / bs), b(bs);
+    switch (dtype) {
+        case SP_F32:
+            hipLaunchKernelGGL(k_record<float>, g, b, 0, s, static_cast<const float *>(u), scale,
+                               sy, sz, nx, ny, nz, xyz, n, traces);
+            break;
+        case SP_F16:
+            hipLaunchKernelGGL(k_record<_Float16>, g, b, 0, s, static_cast<const _Float16 *>(u),
+                               scale, sy, sz, nx, ny, nz, xyz, n, traces);
+            break;
+        case SP_BF16:
+            hipLaunchKernelGGL(k_record<__bf16>, g, b, 0, s, static_cast<const __bf16 *>(u),
+                               scale, sy, sz, nx, ny, nz, xyz, n, traces);
+            break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

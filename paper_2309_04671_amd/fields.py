@@ -62,3 +62,60 @@ class Field:
 
 def field(nx, ny, nz, dtype=lib.SP_F32, device="cuda") -> Field:
     return Field(lib.grid_init(nx, ny, nz, dtype), device)
+
+
+def nslab(nz: int) -> int:
+    return (nz + lib.SP_SLAB - 1) // lib.SP_SLAB
+
+
+class WaveState:
+    """Two wavefields (u^{n-1}, u^n), their FP16/BF16 slab records, and the
+    sp_wave_state that the library advances.
+
+    The meta block is 4 slots of [scale[nslab] float32, amax[nslab] float32
+    bits]; field u^k uses slot k mod 4 (see include/stencil.h).
+    """
+
+    def __init__(self, grid: lib.sp_grid, device="cuda"):
+        self.grid = grid
+        self.a = Field(grid, device)
+        self.b = Field(grid, device)
+        nbytes = int(lib.load().sp_wave_meta_bytes(grid))
+        self.meta = torch.zeros(max(nbytes // 4, 1), dtype=torch.float32, device=device)
+        self.st = lib.sp_wave_state(self.b.ptr, self.a.ptr,
+                                    self.meta.data_ptr() if nbytes else None, 0)
+
+    @property
+    def nslab(self) -> int:
+        return nslab(self.grid.nz)
+
+    def _by_ptr(self, p) -> Field:
+        return self.a if p == self.a.ptr else self.b
+
+    def cur(self) -> Field:
+        return self._by_ptr(self.st.cur)
+
+    def prev(self) -> Field:
+        return self._by_ptr(self.st.prev)
+
+    def slot(self, k: int):
+        """(scale, amax) float32 views of the records of field u^k."""
+        n = self.nslab
+        base = (k % 4) * 2 * n
+        return self.meta[base:base + n], self.meta[base + n:base + 2 * n]
+
+    def reset(self):
+        self.a.buf.zero_()
+        self.b.buf.zero_()
+        self.meta.zero_()
+        self.st.cur, self.st.prev, self.st.step = self.b.ptr, self.a.ptr, 0
+
+    def decoded(self, which="cur") -> np.ndarray:
+        """Interior of u^n (or u^{n-1}) decoded to FP64 with its slab scales."""
+        f = self.cur() if which == "cur" else self.prev()
+        q = f.get_interior().astype(np.float64)
+        if self.grid.dtype == lib.SP_F32:
+            return q
+        k = self.st.step if which == "cur" else self.st.step - 1
+        s = self.slot(k)[0].cpu().numpy().astype(np.float64)
+        return q * s[np.arange(self.grid.nz) // lib.SP_SLAB][:, None, None]

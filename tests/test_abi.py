@@ -123,3 +123,14 @@ def test_wave_step_validates_before_launch():
     assert call(rec=rec) == lib.SP_EINVAL
     # the state must be untouched by a rejected call
     assert st.cur == 1 << 30 and st.step == 0
+
+
+def test_unknown_tile_override_is_rejected(monkeypatch):
+    monkeypatch.setenv("SP_TILE", "96x7x1")
+    L = lib.load()
+    g = lib.grid_init(16, 16, 16)
+    c = lib.coeffs({"center": -1, "ax": [0] * 4, "ay": [0] * 4, "az": [0] * 4})
+    out = ctypes.c_int()
+    rc = L.sp_stencil_apply(ctypes.byref(g), ctypes.byref(c), 1, ctypes.c_void_p(1 << 30),
+                            ctypes.c_void_p(1 << 40), ctypes.byref(out), None)
+    assert rc == lib.SP_EINVAL and "not compiled" in lib.last_error()

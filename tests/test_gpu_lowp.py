@@ -1,0 +1,123 @@
+"""GPU parity of FP16/BF16 wavefield storage against the storage emulation
+(oracle/lowp.py) and the FP64 oracle.
+
+Bars:
+ * one step from the same stored state: the new slab scales are equal
+   exactly (the exponent decision is taken in FP32 on both sides); every
+   stored value is within 1 ulp of the storage format of the emulation's,
+   plus the FP32 arithmetic bound of the kernel (2^-4 in stored units, from
+   |terms| <= 8 max|inputs| <= 2^15 scaled units and ~32 roundings);
+ * the recorded slab maxima equal max|stored| * scale of the GPU's own output;
+ * multi-step runs: error against the FP64 oracle is reported and must stay
+   within twice the emulation's own storage error.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import lowp
+import synth
+from tests.gpu_util import errors
+
+pytestmark = pytest.mark.gpu
+
+FMT = {"f16": 1, "bf16": 2}
+TDT = {"f16": torch.float16, "bf16": torch.bfloat16}
+
+
+def _state_from(fields, g, q_prev, s_prev, q_cur, s_cur, fmt):
+    ws = fields.WaveState(g)
+    ws.prev().set_interior(q_prev.astype(np.float32))
+    ws.cur().set_interior(q_cur.astype(np.float32))
+    sc, ac = ws.slot(0)
+    sp, ap = ws.slot(-1)
+    sc.copy_(torch.tensor(s_cur))
+    sp.copy_(torch.tensor(s_prev))
+    ac.copy_(torch.tensor(lowp.slab_amax(q_cur, s_cur)))
+    ap.copy_(torch.tensor(lowp.slab_amax(q_prev, s_prev)))
+    return ws
+
+
+@pytest.mark.parametrize("fmt", ["f16", "bf16"])
+def test_single_step_parity(gpu_lib, fmt):
+    from paper_2309_04671_amd import fields, lib
+    nx, ny, nz = 301, 45, 70                    # ragged in x, y and in the last slab
+    g = lib.grid_init(nx, ny, nz, FMT[fmt])
+    gv = lib.grid_init(nx, ny, nz)
+    v = synth.layered_velocity(nx, ny, nz, 3)
+    V = fields.Field(gv).set_interior(v)
+    dx = 10.0
+    dt = synth.cfl_dt(v, dx)
+    co = synth.star25_coeffs()
+    rng = np.random.default_rng(12)
+    n = lowp.nslab(nz)
+    # per-slab magnitudes spanning several binades
+    mag = 2.0 ** rng.integers(-20, 4, n)
+    plane_mag = mag[np.arange(nz) // 16][:, None, None]
+    s_cur = (2.0 ** (np.ceil(np.log2(mag)) - 14)).astype(np.float32)
+    s_prev = (s_cur * 2).astype(np.float32)
+    q_cur = lowp.round_to(rng.uniform(-1, 1, (nz, ny, nx)) * plane_mag / lowp.plane_scales(s_cur, nz)[:, None, None], fmt)
+    q_prev = lowp.round_to(rng.uniform(-1, 1, (nz, ny, nx)) * plane_mag / lowp.plane_scales(s_prev, nz)[:, None, None], fmt)
+    ws = _state_from(fields, g, q_prev, s_prev, q_cur, s_cur, fmt)
+    src_xyz = np.array([[150, 22, 35], [300, 44, 69]], np.int32)
+    amp = torch.tensor([[3.0e-3, -2.0e2]], dtype=torch.float32, device="cuda")
+    lib.sp_wave_step(g, lib.coeffs(co), dt, dx, gv, V.ptr, ws.st, 1,
+                     src=lib.make_sources(src_xyz, amp.data_ptr(), 2))
+    torch.cuda.synchronize()
+    assert ws.st.step == 1
+    q_gpu = ws.cur().get_interior().astype(np.float64)
+    s_gpu = ws.slot(1)[0].cpu().numpy()
+    a_gpu = ws.slot(1)[1].cpu().numpy()
+    q_ref, s_ref, a_ref, u_ref = lowp.step(co, v, dt, dx, fmt, q_prev, s_prev,
+                                           lowp.slab_amax(q_prev, s_prev), q_cur, s_cur,
+                                           lowp.slab_amax(q_cur, s_cur), src=src_xyz,
+                                           amp_row=amp[0].cpu().numpy())
+    assert np.array_equal(s_gpu, s_ref)
+    tol = lowp.ulp(q_ref, fmt) + 2.0 ** -4
+    d = np.abs(q_gpu - q_ref)
+    exact = float(np.mean(d == 0))
+    print(fmt, "one step: max |dq| / ulp = %.3f, exact fraction %.5f" % (
+        float(np.max(d / lowp.ulp(q_ref, fmt))), exact))
+    assert np.all(d <= tol)
+    assert exact > 0.95
+    assert np.array_equal(a_gpu, lowp.slab_amax(q_gpu, s_gpu))
+    assert np.max(np.abs(q_gpu)) <= 2 ** 15
+    # the slot of u^{n+2} was cleared for the next step
+    assert np.all(ws.slot(2)[0].cpu().numpy() == 0) and np.all(ws.slot(2)[1].cpu().numpy() == 0)
+    # decoded error against the exact FP64 step is the storage rounding
+    e = errors(ws.decoded(), u_ref)
+    assert e["rel_l2"] <= (2.0 ** -11 if fmt == "f16" else 2.0 ** -8)
+
+
+@pytest.mark.parametrize("fmt", ["f16", "bf16"])
+def test_multi_step_with_receivers(gpu_lib, fmt):
+    from paper_2309_04671_amd import fields, lib
+    nx, ny, nz = 72, 40, 52
+    steps = 60
+    p = synth.wave_problem(nx, ny, nz, steps, seed=4)
+    g = lib.grid_init(nx, ny, nz, FMT[fmt])
+    gv = lib.grid_init(nx, ny, nz)
+    V = fields.Field(gv).set_interior(p["v"])
+    co = synth.star25_coeffs()
+    amp = torch.tensor(p["amp"] * 1e3, dtype=torch.float32, device="cuda")
+    rec_xyz = np.concatenate([synth.receiver_plane(nx, ny, 8, 4), np.array([[36, 20, 26]], np.int32)])
+    rec_d = torch.tensor(rec_xyz, dtype=torch.int32, device="cuda")
+    traces = torch.zeros((steps, len(rec_xyz)), dtype=torch.float32, device="cuda")
+    ws = fields.WaveState(g)
+    lib.sp_wave_step(g, lib.coeffs(co), p["dt"], p["dx"], gv, V.ptr, ws.st, steps,
+                     src=lib.make_sources(p["src"], amp.data_ptr(), 1),
+                     rec=lib.make_receivers(len(rec_xyz), rec_d.data_ptr(), traces.data_ptr(),
+                                            len(rec_xyz)))
+    torch.cuda.synchronize()
+    got = ws.decoded()
+    a64 = amp.cpu().double().numpy()
+    ref = oracle.wave_run(co, p["v"], p["dt"], p["dx"], steps, src=p["src"], amp=a64, rec=rec_xyz)
+    emu, emu_tr = lowp.run(co, p["v"], p["dt"], p["dx"], fmt, steps, p["src"], a64, rec=rec_xyz)
+    e_gpu = errors(got, oracle.interior(ref["cur"]))
+    e_emu = errors(emu, oracle.interior(ref["cur"]))
+    print(fmt, "60 steps vs FP64 oracle: GPU", e_gpu, "emulation", e_emu)
+    assert e_gpu["rel_l2"] <= 2 * e_emu["rel_l2"] + 1e-6
+    et = errors(traces.cpu().numpy(), ref["traces"])
+    assert et["rel_l2"] <= 4 * errors(emu_tr, ref["traces"])["rel_l2"] + 1e-6
