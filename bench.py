@@ -85,6 +85,122 @@ def cpu_baseline(min_seconds=10.0):
                       % (nx, ny, nz, steps, elapsed)}
 
 
+def leg_storage(torch, lib, fields, synth, steps=2, nt=1000, n=512):
+    """FP32 vs FP16-store vs BF16-store leapfrog on n^3, nt steps (same model,
+    same source); GPts/s and HBM fraction at each form's algorithmic bytes."""
+    out = {}
+    vel = synth.layered_velocity(n, n, n, 0)
+    dx = 10.0
+    dt = synth.cfl_dt(vel, dx)
+    gv = lib.grid_init(n, n, n, lib.SP_F32)
+    V = fields.Field(gv).set_interior(vel)
+    del vel
+    amp = torch.tensor(synth.ricker(nt, dt, 15.0)[:, None], dtype=torch.float32, device="cuda")
+    src = lib.make_sources([[n // 2, n // 2, n // 2]], amp.data_ptr(), 1)
+    co = lib.coeffs(synth.star25_coeffs())
+    stream = torch.cuda.current_stream()
+    for name, dtype, bpp in (("fp32", lib.SP_F32, 16), ("fp16_store", lib.SP_F16, 10),
+                             ("bf16_store", lib.SP_BF16, 10)):
+        g = lib.grid_init(n, n, n, dtype)
+        ws = fields.WaveState(g)
+        ev = []
+        for it in range(steps + 1):
+            ws.reset()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            lib.sp_wave_step(g, co, dt, dx, gv, V.ptr, ws.st, nt, src=src, stream=stream)
+            e1.record(stream)
+            if it > 0:
+                ev.append((e0, e1))
+        torch.cuda.synchronize()
+        ms = sum(a.elapsed_time(b) for a, b in ev) / len(ev)
+        gpts = n ** 3 * nt / (ms / 1e3) / 1e9
+        out[name] = {"gpts": round(gpts, 2), "ms_per_sim": round(ms, 2),
+                     "bytes_per_point": bpp,
+                     "hbm_frac": round(gpts * bpp / HBM_PEAK_GBS, 4),
+                     "finite": bool(torch.isfinite(ws.cur().interior().float()).all())}
+        del ws
+    out["fp16_vs_fp32_speed"] = round(out["fp16_store"]["gpts"] / out["fp32"]["gpts"], 3)
+    out["bf16_vs_fp32_speed"] = round(out["bf16_store"]["gpts"] / out["fp32"]["gpts"], 3)
+    out["config"] = "%d^3, %d steps, layered v seed 0, Ricker 15 Hz at centre" % (n, nt)
+    return out
+
+
+def leg_storage_error(torch, lib, fields, synth, n=128, nt=1000):
+    """Error of each storage form against the FP64 oracle after nt steps."""
+    import numpy as np
+    import oracle
+    vel = synth.layered_velocity(n, n, n, 0)
+    dx = 10.0
+    dt = synth.cfl_dt(vel, dx)
+    w = synth.ricker(nt, dt, 15.0)[:, None]
+    amp32 = w.astype(np.float32)
+    src = np.array([[n // 2, n // 2, n // 2]], np.int32)
+    co_d = synth.star25_coeffs()
+    t0 = time.perf_counter()
+    ref = oracle.interior(oracle.wave_run(co_d, vel, dt, dx, nt, src=src,
+                                          amp=amp32.astype(np.float64))["cur"])
+    t_oracle = time.perf_counter() - t0
+    gv = lib.grid_init(n, n, n, lib.SP_F32)
+    V = fields.Field(gv).set_interior(vel)
+    amp = torch.tensor(amp32, device="cuda")
+    co = lib.coeffs(co_d)
+    out = {"config": "%d^3, %d steps, vs FP64 oracle (%.1f s on CPU)" % (n, nt, t_oracle)}
+    nref = float(np.linalg.norm(ref))
+    for name, dtype in (("fp32", lib.SP_F32), ("fp16_store", lib.SP_F16), ("bf16_store", lib.SP_BF16)):
+        g = lib.grid_init(n, n, n, dtype)
+        ws = fields.WaveState(g)
+        lib.sp_wave_step(g, co, dt, dx, gv, V.ptr, ws.st, nt,
+                         src=lib.make_sources(src, amp.data_ptr(), 1))
+        torch.cuda.synchronize()
+        d = ws.decoded() - ref
+        out[name] = {"rel_l2": float(np.linalg.norm(d) / nref), "max_abs": float(np.max(np.abs(d))),
+                     "rmsd": float(np.sqrt(np.mean(d * d))), "ref_max": float(np.max(np.abs(ref)))}
+    return out
+
+
+def leg_adjoint(torch, lib, fields, synth, n=256, nt=1000, ckpt=32):
+    """Misfit gradient at n^3 x nt (checkpoint every ckpt steps): wall time of
+    forward + backward against the plain forward run."""
+    import numpy as np
+    from paper_2309_04671_amd.adjoint import WaveOp, WaveProblem
+    v = synth.layered_velocity(n, n, n, 0)
+    v0 = synth.gaussian_bump(v, (n // 2, n // 2, n // 2), 10.0, 0.10)
+    v_obs = synth.gaussian_bump(v0, (96 * n // 256, 160 * n // 256, 160 * n // 256), 12.0, 0.05)
+    dx = 10.0
+    dt = synth.cfl_dt(v0, dx)
+    src = np.array([[n // 2, n // 2, 8]], np.int32)
+    rec = synth.receiver_plane(n, n, 8, 2)
+    amp = synth.ricker(nt, dt, 15.0)[:, None]
+    prob = WaveProblem(n, n, n, synth.star25_coeffs(), dt, dx, nt, src, amp, rec, ckpt=ckpt)
+    with torch.no_grad():
+        d_obs = WaveOp.apply(torch.tensor(v_obs, device="cuda"), prob).double()
+    vt = torch.tensor(v0, device="cuda")
+    # plain forward
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.no_grad():
+        WaveOp.apply(vt, prob)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    vv = vt.clone().requires_grad_(True)
+    tr = WaveOp.apply(vv, prob)
+    J = 0.5 * ((tr.double() - d_obs) ** 2).sum()
+    J.backward()
+    torch.cuda.synchronize()
+    t_all = time.perf_counter() - t0
+    g = vv.grad
+    bytes_per_step = 72      # forward 16 + recompute 16 + adjoint step 16 + gradient 24 (B/pt)
+    return {"config": "%d^3, %d steps, checkpoint every %d, %d receivers" % (n, nt, ckpt, len(rec)),
+            "forward_s": round(t_fwd, 4), "forward_backward_s": round(t_all, 4),
+            "ratio_vs_forward": round(t_all / t_fwd, 3),
+            "effective_gbs": round(n ** 3 * nt * bytes_per_step / t_all / 1e9, 1),
+            "misfit": float(J.detach()), "grad_finite": bool(torch.isfinite(g).all()),
+            "grad_norm": float(g.double().norm())}
+
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +210,8 @@ def main():
     ap.add_argument("--nt", type=int, default=NSTEPS,
                     help="time steps per simulation (default: the workload's 500; fewer only for "
                          "profiling runs)")
+    ap.add_argument("--legs", default="storage,storage_error,adjoint",
+                    help="extra measurements after the headline run (comma list; '' for none)")
     ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
                     help="instead of the benchmark, copy a GIB-sized buffer 4 times with torch "
                          "(reference kernel for the HBM byte counters)")
@@ -199,6 +317,21 @@ def main():
         "hbm_frac_of_wall": round(gpts * BYTES_PER_POINT / HBM_PEAK_GBS, 4),
         "gflops": round(gpts * FLOPS_PER_POINT, 1),
     }
+    del P, C, V
+    torch.cuda.empty_cache()
+    legs = [x for x in args.legs.split(",") if x]
+    forms = {}
+    if "storage" in legs:
+        log("storage forms at 512^3")
+        forms["storage_512"] = leg_storage(torch, lib, fields, synth)
+    if "storage_error" in legs:
+        log("storage error at 128^3 vs the FP64 oracle")
+        forms["storage_error_128"] = leg_storage_error(torch, lib, fields, synth)
+    if "adjoint" in legs:
+        log("adjoint gradient at 256^3")
+        forms["adjoint_256"] = leg_adjoint(torch, lib, fields, synth)
+    if forms:
+        out["forms"] = forms
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline()

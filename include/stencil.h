@@ -171,6 +171,63 @@ int sp_wave_step(const sp_grid *g, const sp_coeffs *c, double dt, double dx,
                  const sp_grid *gv, const float *v, sp_wave_state *st, int nsteps,
                  const sp_sources *src, const sp_receivers *rec, void *stream);
 
+/*
+ * sp_wave_run_states -- leapfrog steps that keep every state (FP32 grids
+ * only): the recompute primitive of checkpointed adjoints.  states is a HOST
+ * array of nsteps+2 DEVICE field pointers (grid g): states[0] = u^{n0-1} and
+ * states[1] = u^{n0} on entry; step i writes u^{n0+i+1} into states[i+2]
+ * (same update, sources and receivers as sp_wave_step, with n = n0 + i;
+ * traces row i).  All pointers must be distinct allocations.
+ */
+int sp_wave_run_states(const sp_grid *g, const sp_coeffs *c, double dt, double dx,
+                       const sp_grid *gv, const float *v, void *const *states, int64_t n0,
+                       int nsteps, const sp_sources *src, const sp_receivers *rec,
+                       void *stream);
+
+/*
+ * sp_wave_adjoint_step -- `nsteps` steps of the discrete adjoint of the
+ * leapfrog for a misfit L(traces), in the scaled variable nu = m * lambda
+ * (FP32 grids only).  With g_k = dL/dtraces row k (the receiver samples of
+ * u^{k+1}), one adjoint step for time index k (k = N .. 1) computes
+ *     nu^k = 2 nu^{k+1} - nu^{k+2} + m * (L nu^{k+1}) + m * R^T g_{k-1}
+ * and accumulates, in FP64,
+ *     G += nu^k * (L u^{k-1} + dx^2 f^{k-1} e_src),
+ * where f are the forward source amplitudes.  After the step for k = 1,
+ * dL/dv = 2 G / v (sp_grad_finish); dt and dx are held fixed.
+ *   adj: adj->cur = nu^{k+1}, adj->prev = nu^{k+2}, adj->step = k on entry
+ *        (zero fields and step = N to start); nu^k is written over prev,
+ *        the pointers swapped and step decremented per step.
+ *   u_hist: HOST array of nsteps DEVICE pointers, u_hist[i] = u^{k-1-i}.
+ *   rec: receivers; rec->traces is READ (dL/dtraces, row k-1 at
+ *        rec->traces + (k-1) * trace_stride).  Receiver points add (duplicates sum).
+ *   src: the forward sources (amplitude row k-1 is read); may be NULL.
+ *   G: DEVICE FP64 array laid out like grid g's elements (g->elems doubles,
+ *      same element offsets); only interior elements are read or written.
+ */
+int sp_wave_adjoint_step(const sp_grid *g, const sp_coeffs *c, double dt, double dx,
+                         const sp_grid *gv, const float *v, sp_wave_state *adj,
+                         const void *const *u_hist, int nsteps, const sp_sources *src,
+                         const sp_receivers *rec, double *G, void *stream);
+
+/* out = 2 G / v on the interior; out is an FP32 field on grid gv (G on the
+ * same element layout, FP64). */
+int sp_grad_finish(const sp_grid *gv, const float *v, const double *G, float *out,
+                   void *stream);
+
+/*
+ * sp_energy -- discrete energy between u0 = u^n and u1 = u^{n+1} (FP32
+ * grids), accumulated in FP64:
+ *     E = sum (u1 - u0)^2 / m - sum u1 * (L u0),   m = (v dt / dx)^2,
+ * which the source-free leapfrog conserves exactly when L is symmetric (zero
+ * halo).  Writes one double to *out (DEVICE).  ws: DEVICE workspace of
+ * sp_energy_ws_bytes(g) bytes (per-block partial sums, added in a fixed
+ * order, so the result is deterministic).
+ */
+int64_t sp_energy_ws_bytes(const sp_grid *g);
+int sp_energy(const sp_grid *g, const sp_coeffs *c, double dt, double dx,
+              const sp_grid *gv, const float *v, const void *u0, const void *u1,
+              double *out, void *ws, void *stream);
+
 /* Thread-local message for the last error on this thread ("" if none). */
 const char *sp_last_error(void);
 

@@ -170,68 +170,87 @@ int64_t sp_wave_meta_bytes(const sp_grid *g) {
     return 4 * 2 * nslab * (int64_t)sizeof(float);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Validation and argument setup shared by the leapfrog entry points.
+int prep_wave(const char *who, const sp_grid *g, const sp_coeffs *c, double dt, double dx,
+              const sp_grid *gv, const float *v, const sp_sources *src, const sp_receivers *rec,
+              sp::SweepArgs *a, sp::TileCfg *t) {
+    if (int e = check_grid(g, who)) return e;
+    if (int e = check_grid(gv, who)) return e;
+    if (gv->dtype != SP_F32 || gv->nx != g->nx || gv->ny != g->ny || gv->nz != g->nz)
+        return fail(SP_EINVAL, "%s: v must be an FP32 grid of the same shape", who);
+    if (!c || !v) return fail(SP_EINVAL, "%s: NULL argument", who);
+    if (!(dt > 0) || !(dx > 0)) return fail(SP_EINVAL, "%s: dt and dx must be > 0", who);
+    if (!aligned16(v)) return fail(SP_EINVAL, "%s: pointers must be 16-byte aligned", who);
+    int nsrc = 0;
+    if (src) {
+        if (src->n < 0 || src->n > SP_MAX_SOURCES)
+            return fail(SP_EINVAL, "%s: %d sources (max %d)", who, src->n, SP_MAX_SOURCES);
+        nsrc = src->n;
+        if (nsrc > 0 && !src->amp) return fail(SP_EINVAL, "%s: source amplitudes are NULL", who);
+        if (nsrc > 0 && src->amp_stride < nsrc) return fail(SP_EINVAL, "%s: amp_stride < n", who);
+        for (int s = 0; s < nsrc; ++s) {
+            const int *p = src->xyz[s];
+            if (p[0] < 0 || p[0] >= g->nx || p[1] < 0 || p[1] >= g->ny || p[2] < 0 || p[2] >= g->nz)
+                return fail(SP_EINVAL, "%s: source %d outside the interior", who, s);
+        }
+    }
+    if (rec) {
+        if (rec->n < 0) return fail(SP_EINVAL, "%s: negative receiver count", who);
+        if (rec->n > 0 && (!rec->xyz || !rec->traces))
+            return fail(SP_EINVAL, "%s: receiver arrays are NULL", who);
+        if (rec->n > 0 && rec->trace_stride < rec->n)
+            return fail(SP_EINVAL, "%s: trace_stride < n", who);
+    }
+    if (!tiles_for(g, t, who)) return SP_EINVAL;
+    std::memset(a, 0, sizeof *a);
+    a->nx = g->nx;
+    a->ny = g->ny;
+    a->nz = g->nz;
+    a->sy = g->pitch_x;
+    a->sz = g->pitch_x * g->pitch_y;
+    a->vsy = gv->pitch_x;
+    a->vsz = gv->pitch_x * gv->pitch_y;
+    a->v = v + gv->origin;
+    a->m_scale = (float)((dt / dx) * (dt / dx));
+    a->c = to_f32(c);
+    a->src.n = nsrc;
+    a->src.dt2 = (float)(dt * dt);
+    for (int s = 0; s < nsrc; ++s) {
+        a->src.x[s] = src->xyz[s][0];
+        a->src.y[s] = src->xyz[s][1];
+        a->src.z[s] = src->xyz[s][2];
+    }
+    fill_tiling(*a, *t);
+    return SP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int sp_wave_step(const sp_grid *g, const sp_coeffs *c, double dt, double dx, const sp_grid *gv,
                  const float *v, sp_wave_state *st, int nsteps, const sp_sources *src,
                  const sp_receivers *rec, void *stream) {
-    if (int e = check_grid(g, "sp_wave_step")) return e;
-    if (int e = check_grid(gv, "sp_wave_step(v)")) return e;
-    if (gv->dtype != SP_F32 || gv->nx != g->nx || gv->ny != g->ny || gv->nz != g->nz)
-        return fail(SP_EINVAL, "sp_wave_step: v must be an FP32 grid of the same shape");
-    if (!c || !v || !st || !st->cur || !st->prev) return fail(SP_EINVAL, "sp_wave_step: NULL argument");
+    sp::SweepArgs a;
+    sp::TileCfg t;
+    if (int e = prep_wave("sp_wave_step", g, c, dt, dx, gv, v, src, rec, &a, &t)) return e;
+    if (!st || !st->cur || !st->prev) return fail(SP_EINVAL, "sp_wave_step: NULL state");
     if (g->dtype == SP_F32 && st->meta) return fail(SP_EINVAL, "sp_wave_step: meta must be NULL for FP32 grids");
     if (g->dtype != SP_F32 && (!st->meta || !aligned16(st->meta)))
         return fail(SP_EINVAL, "sp_wave_step: FP16/BF16 grids need a 16-byte aligned meta block");
     if (nsteps < 0) return fail(SP_EINVAL, "sp_wave_step: nsteps < 0");
-    if (!(dt > 0) || !(dx > 0)) return fail(SP_EINVAL, "sp_wave_step: dt and dx must be > 0");
-    if (!aligned16(st->cur) || !aligned16(st->prev) || !aligned16(v))
+    if (!aligned16(st->cur) || !aligned16(st->prev))
         return fail(SP_EINVAL, "sp_wave_step: pointers must be 16-byte aligned");
     if (overlaps(st->cur, st->prev, g->bytes)) return fail(SP_EINVAL, "sp_wave_step: cur and prev overlap");
     if (overlaps(st->cur, v, g->bytes) || overlaps(st->prev, v, g->bytes))
         return fail(SP_EINVAL, "sp_wave_step: v overlaps a wavefield");
     if (st->step < 0) return fail(SP_EINVAL, "sp_wave_step: negative step counter");
-    int nsrc = 0;
-    if (src) {
-        if (src->n < 0 || src->n > SP_MAX_SOURCES)
-            return fail(SP_EINVAL, "sp_wave_step: %d sources (max %d)", src->n, SP_MAX_SOURCES);
-        nsrc = src->n;
-        if (nsrc > 0 && !src->amp) return fail(SP_EINVAL, "sp_wave_step: source amplitudes are NULL");
-        if (nsrc > 0 && src->amp_stride < nsrc) return fail(SP_EINVAL, "sp_wave_step: amp_stride < n");
-        for (int s = 0; s < nsrc; ++s) {
-            const int *p = src->xyz[s];
-            if (p[0] < 0 || p[0] >= g->nx || p[1] < 0 || p[1] >= g->ny || p[2] < 0 || p[2] >= g->nz)
-                return fail(SP_EINVAL, "sp_wave_step: source %d outside the interior", s);
-        }
-    }
-    int nrec = 0;
-    if (rec) {
-        if (rec->n < 0) return fail(SP_EINVAL, "sp_wave_step: negative receiver count");
-        nrec = rec->n;
-        if (nrec > 0 && (!rec->xyz || !rec->traces)) return fail(SP_EINVAL, "sp_wave_step: receiver arrays are NULL");
-        if (nrec > 0 && rec->trace_stride < nrec) return fail(SP_EINVAL, "sp_wave_step: trace_stride < n");
-    }
-
-    sp::SweepArgs a;
-    std::memset(&a, 0, sizeof a);
-    a.nx = g->nx;
-    a.ny = g->ny;
-    a.nz = g->nz;
-    a.sy = g->pitch_x;
-    a.sz = g->pitch_x * g->pitch_y;
-    a.vsy = gv->pitch_x;
-    a.vsz = gv->pitch_x * gv->pitch_y;
-    a.v = v + gv->origin;
-    a.m_scale = (float)((dt / dx) * (dt / dx));
-    a.c = to_f32(c);
-    a.src.n = nsrc;
-    a.src.dt2 = (float)(dt * dt);
-    for (int s = 0; s < nsrc; ++s) {
-        a.src.x[s] = src->xyz[s][0];
-        a.src.y[s] = src->xyz[s][1];
-        a.src.z[s] = src->xyz[s][2];
-    }
-    sp::TileCfg t;
-    if (!tiles_for(g, &t, "sp_wave_step")) return SP_EINVAL;
-    fill_tiling(a, t);
+    const int nsrc = a.src.n;
+    const int nrec = rec ? rec->n : 0;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t step0 = st->step;
     const int64_t eb = g->elem_bytes;
@@ -271,6 +290,139 @@ int sp_wave_step(const sp_grid *g, const sp_coeffs *c, double dt, double dx, con
         std::swap(st->cur, st->prev);
         st->step += 1;
     }
+    return ok();
+}
+
+int sp_wave_run_states(const sp_grid *g, const sp_coeffs *c, double dt, double dx,
+                       const sp_grid *gv, const float *v, void *const *states, int64_t n0,
+                       int nsteps, const sp_sources *src, const sp_receivers *rec, void *stream) {
+    sp::SweepArgs a;
+    sp::TileCfg t;
+    if (int e = prep_wave("sp_wave_run_states", g, c, dt, dx, gv, v, src, rec, &a, &t)) return e;
+    if (g->dtype != SP_F32) return fail(SP_EUNSUPPORTED, "sp_wave_run_states: FP32 grids only");
+    if (nsteps < 0 || n0 < 0) return fail(SP_EINVAL, "sp_wave_run_states: negative nsteps or n0");
+    if (!states) return fail(SP_EINVAL, "sp_wave_run_states: states is NULL");
+    for (int i = 0; i < nsteps + 2; ++i) {
+        if (!states[i] || !aligned16(states[i]))
+            return fail(SP_EINVAL, "sp_wave_run_states: state %d NULL or misaligned", i);
+        if (overlaps(states[i], v, g->bytes)) return fail(SP_EINVAL, "sp_wave_run_states: v overlaps a state");
+        for (int j = (i > 2 ? i - 2 : 0); j < i; ++j)
+            if (overlaps(states[i], states[j], g->bytes))
+                return fail(SP_EINVAL, "sp_wave_run_states: states %d and %d overlap", j, i);
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int nrec = rec ? rec->n : 0;
+    for (int i = 0; i < nsteps; ++i) {
+        a.prev = static_cast<const float *>(states[i]) + g->origin;
+        a.u = static_cast<const float *>(states[i + 1]) + g->origin;
+        float *out = static_cast<float *>(states[i + 2]) + g->origin;
+        a.out = out;
+        if (a.src.n > 0) a.src.amp = src->amp + (n0 + i) * src->amp_stride;
+        hipError_t err = sp::launch_sweep(sp::MODE_WAVE, SP_F32, t, a, s);
+        if (err == hipSuccess && nrec > 0)
+            err = sp::launch_record(SP_F32, out, nullptr, a.sy, a.sz, g->nx, g->ny, g->nz,
+                                    rec->xyz, nrec, rec->traces + i * rec->trace_stride, s);
+        if (err != hipSuccess)
+            return fail(SP_EDEVICE, "sp_wave_run_states: launch failed: %s", hipGetErrorString(err));
+    }
+    return ok();
+}
+
+int sp_wave_adjoint_step(const sp_grid *g, const sp_coeffs *c, double dt, double dx,
+                         const sp_grid *gv, const float *v, sp_wave_state *adj,
+                         const void *const *u_hist, int nsteps, const sp_sources *src,
+                         const sp_receivers *rec, double *G, void *stream) {
+    sp::SweepArgs a;
+    sp::TileCfg t;
+    if (int e = prep_wave("sp_wave_adjoint_step", g, c, dt, dx, gv, v, src, rec, &a, &t)) return e;
+    if (g->dtype != SP_F32) return fail(SP_EUNSUPPORTED, "sp_wave_adjoint_step: FP32 grids only");
+    if (!adj || !adj->cur || !adj->prev || !G || !u_hist)
+        return fail(SP_EINVAL, "sp_wave_adjoint_step: NULL argument");
+    if (adj->meta) return fail(SP_EINVAL, "sp_wave_adjoint_step: meta must be NULL");
+    if (nsteps < 0) return fail(SP_EINVAL, "sp_wave_adjoint_step: nsteps < 0");
+    if (adj->step < nsteps) return fail(SP_EINVAL, "sp_wave_adjoint_step: step counter below 1");
+    if (!aligned16(adj->cur) || !aligned16(adj->prev) || (reinterpret_cast<uintptr_t>(G) & 31u))
+        return fail(SP_EINVAL, "sp_wave_adjoint_step: misaligned pointer");
+    if (overlaps(adj->cur, adj->prev, g->bytes)) return fail(SP_EINVAL, "sp_wave_adjoint_step: adjoint fields overlap");
+    for (int i = 0; i < nsteps; ++i) {
+        if (!u_hist[i] || !aligned16(u_hist[i]))
+            return fail(SP_EINVAL, "sp_wave_adjoint_step: u_hist[%d] NULL or misaligned", i);
+        if (overlaps(u_hist[i], adj->cur, g->bytes) || overlaps(u_hist[i], adj->prev, g->bytes))
+            return fail(SP_EINVAL, "sp_wave_adjoint_step: u_hist[%d] overlaps an adjoint field", i);
+    }
+    const int nrec = rec ? rec->n : 0;
+    const sp::SrcList fwd_src = a.src;      // forward sources: gradient term only
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const float inj_scale = (float)((dt / dx) * (dt / dx));   // m g = dt^2 v^2 g / dx^2
+    for (int i = 0; i < nsteps; ++i) {
+        const int64_t k = adj->step;
+        float *nu1 = static_cast<float *>(adj->cur) + g->origin;    // nu^{k+1}
+        float *nu2 = static_cast<float *>(adj->prev) + g->origin;   // nu^{k+2} -> nu^k
+        a.src.n = 0;
+        a.u = nu1;
+        a.prev = nu2;
+        a.out = nu2;
+        hipError_t err = sp::launch_sweep(sp::MODE_WAVE, SP_F32, t, a, s);
+        if (err == hipSuccess && nrec > 0)
+            err = sp::launch_inject(nu2, a.sy, a.sz, a.v, a.vsy, a.vsz, g->nx, g->ny, g->nz,
+                                    rec->xyz, nrec, rec->traces + (k - 1) * rec->trace_stride,
+                                    inj_scale, s);
+        if (err == hipSuccess) {
+            sp::SweepArgs ga = a;
+            ga.src = fwd_src;
+            if (ga.src.n > 0) ga.src.amp = src->amp + (k - 1) * src->amp_stride;
+            ga.u = static_cast<const float *>(u_hist[i]) + g->origin;
+            ga.prev = nu2;
+            ga.out = nullptr;
+            ga.gacc = G + g->origin;
+            ga.dx2 = (float)(dx * dx);
+            err = sp::launch_sweep(sp::MODE_GRAD, SP_F32, t, ga, s);
+        }
+        if (err != hipSuccess)
+            return fail(SP_EDEVICE, "sp_wave_adjoint_step: launch failed at k=%lld: %s",
+                        (long long)k, hipGetErrorString(err));
+        std::swap(adj->cur, adj->prev);
+        adj->step -= 1;
+    }
+    return ok();
+}
+
+int sp_grad_finish(const sp_grid *gv, const float *v, const double *G, float *out, void *stream) {
+    if (int e = check_grid(gv, "sp_grad_finish")) return e;
+    if (gv->dtype != SP_F32) return fail(SP_EINVAL, "sp_grad_finish: v must be an FP32 grid");
+    if (!v || !G || !out) return fail(SP_EINVAL, "sp_grad_finish: NULL argument");
+    if (overlaps(out, v, gv->bytes)) return fail(SP_EINVAL, "sp_grad_finish: out overlaps v");
+    hipError_t err = sp::launch_grad_finish(G + gv->origin, v + gv->origin, out + gv->origin,
+                                            gv->pitch_x, gv->pitch_x * gv->pitch_y, gv->nx,
+                                            gv->ny, gv->nz, static_cast<hipStream_t>(stream));
+    if (err != hipSuccess) return fail(SP_EDEVICE, "sp_grad_finish: %s", hipGetErrorString(err));
+    return ok();
+}
+
+int64_t sp_energy_ws_bytes(const sp_grid *g) {
+    if (!g || g->nx < 1 || g->ny < 1 || g->nz < 1) return 0;
+    // upper bound over every compiled tile shape (smallest: 64 x 8) and z-chunk
+    return (int64_t)((g->nx + 63) / 64) * ((g->ny + 7) / 8) * g->nz * (int64_t)sizeof(double);
+}
+
+int sp_energy(const sp_grid *g, const sp_coeffs *c, double dt, double dx, const sp_grid *gv,
+              const float *v, const void *u0, const void *u1, double *out, void *ws, void *stream) {
+    sp::SweepArgs a;
+    sp::TileCfg t;
+    if (int e = prep_wave("sp_energy", g, c, dt, dx, gv, v, nullptr, nullptr, &a, &t)) return e;
+    if (g->dtype != SP_F32) return fail(SP_EUNSUPPORTED, "sp_energy: FP32 grids only");
+    if (!u0 || !u1 || !out || !ws) return fail(SP_EINVAL, "sp_energy: NULL argument");
+    if (!aligned16(u0) || !aligned16(u1) || (reinterpret_cast<uintptr_t>(ws) & 7u))
+        return fail(SP_EINVAL, "sp_energy: misaligned pointer");
+    const int nblk = a.tiles_x * a.tiles_y * a.nzc;
+    if ((int64_t)nblk * 8 > sp_energy_ws_bytes(g)) return fail(SP_ENOMEM, "sp_energy: workspace too small");
+    a.u = static_cast<const float *>(u0) + g->origin;
+    a.prev = static_cast<const float *>(u1) + g->origin;
+    a.gacc = static_cast<double *>(ws);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t err = sp::launch_sweep(sp::MODE_ENERGY, SP_F32, t, a, s);
+    if (err == hipSuccess) err = sp::launch_sum(static_cast<double *>(ws), nblk, out, s);
+    if (err != hipSuccess) return fail(SP_EDEVICE, "sp_energy: %s", hipGetErrorString(err));
     return ok();
 }
 

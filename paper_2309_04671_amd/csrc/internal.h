@@ -12,6 +12,8 @@ namespace sp {
 enum Mode : int {
     MODE_APPLY = 0,   // out = L u
     MODE_WAVE = 1,    // out = 2u - prev + m L u (+ sources)
+    MODE_GRAD = 2,    // G += w * (L u + dx^2 f e_src)      (FP64 G; w in `prev`)
+    MODE_ENERGY = 3,  // partial[block] = sum (w - u)^2 / m - w L u   (FP64; w in `prev`)
 };
 
 // Stencil weights rounded once to FP32 (paper Eq. 3).
@@ -59,6 +61,8 @@ struct SweepArgs {
     StarCoef c;
     SrcList src;
     SlabMeta meta;       // FP16/BF16 storage only
+    double *gacc;        // MODE_GRAD: FP64 field on the FP32 layout; MODE_ENERGY: partial sums
+    float dx2;           // MODE_GRAD: dx^2 (source term)
     int tiles_x, tiles_y, zchunk, nzc;
 };
 
@@ -76,5 +80,15 @@ hipError_t launch_sweep(int mode, int dtype, const TileCfg &t, const SweepArgs &
 hipError_t launch_record(int dtype, const void *u, const float *scale, int64_t sy, int64_t sz,
                          int nx, int ny, int nz, const int32_t *xyz, int n, float *traces,
                          hipStream_t s);
+
+// field[x_r] += scale * v[x_r]^2 * amp[r] for r < n (atomic: duplicates add).
+hipError_t launch_inject(float *field, int64_t sy, int64_t sz, const float *v, int64_t vsy,
+                         int64_t vsz, int nx, int ny, int nz, const int32_t *xyz, int n,
+                         const float *amp, float scale, hipStream_t s);
+// out = 2 G / v on the interior (FP32 grid layout for out, v; FP64 G).
+hipError_t launch_grad_finish(const double *G, const float *v, float *out, int64_t sy, int64_t sz,
+                              int nx, int ny, int nz, hipStream_t s);
+// *out = sum of n partials, in index order.
+hipError_t launch_sum(const double *partial, int n, double *out, hipStream_t s);
 
 }  // namespace sp

@@ -165,7 +165,9 @@ k_star25(SweepArgs a) {
     constexpr int HC = HY + 2 * TY;      // all halo chunks per plane
     constexpr int HPT = (HC + NT - 1) / NT;
     static_assert(TY % RY == 0, "RY must divide TY");
-    static_assert(MODE == MODE_WAVE || !IO::scaled, "apply is FP32 only");
+    static_assert(MODE == MODE_WAVE || !IO::scaled, "only the leapfrog step has FP16/BF16 storage");
+    typedef double d4v __attribute__((ext_vector_type(4)));
+    constexpr bool PW = (MODE == MODE_WAVE || MODE == MODE_GRAD || MODE == MODE_ENERGY);  // reads `prev`
     __shared__ f4v lds[2][LR][LC];
 
     const int lin = xcd_tile(blockIdx.x, gridDim.x);
@@ -263,11 +265,18 @@ k_star25(SweepArgs a) {
     for (int j = 0; j < RY; ++j) {
         pp[j] = rzero;
         vv[j] = zero;
-        if (MODE == MODE_WAVE && st_ok[j]) {
-            pp[j] = IO::ld_nt(uprev + (int64_t)zb * sz + own[j]);
+        if (PW && st_ok[j]) pp[j] = IO::ld_nt(uprev + (int64_t)zb * sz + own[j]);
+        if ((MODE == MODE_WAVE || MODE == MODE_ENERGY) && st_ok[j])
             vv[j] = ld4_nt(a.v + (int64_t)zb * a.vsz + vown[j]);
-        }
     }
+    d4v gg[RY];
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+        gg[j] = d4v{0.0, 0.0, 0.0, 0.0};
+        if (MODE == MODE_GRAD && st_ok[j])
+            gg[j] = *reinterpret_cast<const d4v *>(a.gacc + (int64_t)zb * sz + own[j]);
+    }
+    double esum = 0.0;                    // MODE_ENERGY: this thread's partial sum
 
     const StarCoef &c = a.c;
     float s_out = 1.f, inv_out = 1.f;     // output scale of the current slab
@@ -295,10 +304,12 @@ k_star25(SweepArgs a) {
 
         raw pp_n[RY];
         f4v vv_n[RY];
+        d4v gg_n[RY];
 #pragma unroll
         for (int j = 0; j < RY; ++j) {
             pp_n[j] = rzero;
             vv_n[j] = zero;
+            gg_n[j] = d4v{0.0, 0.0, 0.0, 0.0};
         }
         if (z + 1 < ze) {
 #pragma unroll
@@ -307,14 +318,16 @@ k_star25(SweepArgs a) {
 #pragma unroll
             for (int j = 0; j < HPT; ++j)
                 hv[j] = h_ok[j] ? IO::ld(u + (int64_t)(z + 1) * sz + hoff[j]) : rzero;
-            if (MODE == MODE_WAVE) {
 #pragma unroll
-                for (int j = 0; j < RY; ++j)
-                    if (st_ok[j]) {
-                        pp_n[j] = IO::ld_nt(uprev + (int64_t)(z + 1) * sz + own[j]);
+            for (int j = 0; j < RY; ++j)
+                if (st_ok[j]) {
+                    if (PW) pp_n[j] = IO::ld_nt(uprev + (int64_t)(z + 1) * sz + own[j]);
+                    if (MODE == MODE_WAVE || MODE == MODE_ENERGY)
                         vv_n[j] = ld4_nt(a.v + (int64_t)(z + 1) * a.vsz + vown[j]);
-                    }
-            }
+                    if (MODE == MODE_GRAD)
+                        gg_n[j] = __builtin_nontemporal_load(
+                            reinterpret_cast<const d4v *>(a.gacc + (int64_t)(z + 1) * sz + own[j]));
+                }
         }
 
         lds_barrier();
@@ -362,6 +375,46 @@ k_star25(SweepArgs a) {
                         }
                     }
                 }
+            } else if (MODE == MODE_GRAD) {
+                // G += w (L u + dx^2 f at sources), products and sums in FP64
+                f4v term = acc;
+                const int y = ybase + j;
+                for (int s = 0; s < a.src.n; ++s) {
+                    if (a.src.z[s] == z && a.src.y[s] == y) {
+                        const int d = a.src.x[s] - x;
+                        if (d >= 0 && d < 4) term[d] += a.dx2 * a.src.amp[s];
+                    }
+                }
+                if (st_ok[j]) {
+                    const f4v w = IO::dec(pp[j], 1.f);
+                    d4v gnew = gg[j];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) gnew[i] = fma((double)w[i], (double)term[i], gnew[i]);
+                    double *go = a.gacc + (int64_t)z * sz + own[j];
+                    if (x + 4 <= a.nx) {
+                        __builtin_nontemporal_store(gnew, reinterpret_cast<d4v *>(go));
+                    } else {
+                        go[0] = gnew[0];
+                        if (x + 1 < a.nx) go[1] = gnew[1];
+                        if (x + 2 < a.nx) go[2] = gnew[2];
+                    }
+                }
+                continue;
+            } else if (MODE == MODE_ENERGY) {
+                // (u1 - u0)^2 / m - u1 (L u0), u0 = ctr, u1 = w; FP64 accumulation
+                if (st_ok[j]) {
+                    const f4v w = IO::dec(pp[j], 1.f);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        if (x + i < a.nx) {
+                            const double vv2 = (double)vv[j][i] * (double)vv[j][i];
+                            const double m = vv2 * (double)a.m_scale;
+                            const double dd = (double)w[i] - (double)ctr[i];
+                            esum += dd * dd / m - (double)w[i] * (double)acc[i];
+                        }
+                    }
+                }
+                continue;
             } else {
                 res = acc;
             }
@@ -403,7 +456,53 @@ k_star25(SweepArgs a) {
             for (int i = 0; i < 8; ++i) q[j][i] = q[j][i + 1];
             pp[j] = pp_n[j];
             vv[j] = vv_n[j];
+            gg[j] = gg_n[j];
         }
+    }
+
+    if constexpr (MODE == MODE_ENERGY) {
+        // block sum in a fixed order: waves by shuffles, then wave 0 over LDS
+        __shared__ double wsum[NT / 64];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) esum += __shfl_xor(esum, off, 64);
+        if ((tid & 63) == 0) wsum[tid >> 6] = esum;
+        __syncthreads();
+        if (tid == 0) {
+            double t = 0.0;
+            for (int w = 0; w < NT / 64; ++w) t += wsum[w];
+            a.gacc[blockIdx.x] = t;
+        }
+    }
+}
+
+__global__ void k_inject(float *field, int64_t sy, int64_t sz, const float *v, int64_t vsy,
+                         int64_t vsz, int nx, int ny, int nz, const int32_t *xyz, int n,
+                         const float *amp, float scale) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int x = xyz[3 * r], y = xyz[3 * r + 1], z = xyz[3 * r + 2];
+    if (x < 0 || x >= nx || y < 0 || y >= ny || z < 0 || z >= nz) return;
+    const float vs = v[(int64_t)z * vsz + (int64_t)y * vsy + x];
+    atomicAdd(field + (int64_t)z * sz + (int64_t)y * sy + x, scale * (vs * vs) * amp[r]);
+}
+
+__global__ void k_grad_finish(const double *G, const float *v, float *out, int64_t sy, int64_t sz,
+                              int nx, int ny, int nz) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = (int64_t)nx * ny * nz;
+    if (i >= n) return;
+    const int x = (int)(i % nx);
+    const int64_t r = i / nx;
+    const int y = (int)(r % ny), z = (int)(r / ny);
+    const int64_t o = (int64_t)z * sz + (int64_t)y * sy + x;
+    out[o] = (float)(2.0 * G[o] / (double)v[o]);
+}
+
+__global__ void k_sum(const double *partial, int n, double *out) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        double t = 0.0;
+        for (int i = 0; i < n; ++i) t += partial[i];
+        *out = t;
     }
 }
 
@@ -428,8 +527,18 @@ hipError_t launch_t(int mode, const SweepArgs &a, hipStream_t s) {
     if (mode == MODE_WAVE) {
         hipLaunchKernelGGL((k_star25<TX, TY, RY, MODE_WAVE, T>), grid, block, 0, s, a);
     } else {
-        if constexpr (Io<T>::scaled) return hipErrorInvalidValue;
-        else hipLaunchKernelGGL((k_star25<TX, TY, RY, MODE_APPLY, T>), grid, block, 0, s, a);
+        if constexpr (Io<T>::scaled) {
+            return hipErrorInvalidValue;
+        } else {
+            if (mode == MODE_APPLY)
+                hipLaunchKernelGGL((k_star25<TX, TY, RY, MODE_APPLY, T>), grid, block, 0, s, a);
+            else if (mode == MODE_GRAD)
+                hipLaunchKernelGGL((k_star25<TX, TY, RY, MODE_GRAD, T>), grid, block, 0, s, a);
+            else if (mode == MODE_ENERGY)
+                hipLaunchKernelGGL((k_star25<TX, TY, RY, MODE_ENERGY, T>), grid, block, 0, s, a);
+            else
+                return hipErrorInvalidValue;
+        }
     }
     return hipGetLastError();
 }
@@ -483,6 +592,30 @@ hipError_t launch_sweep(int mode, int dtype, const TileCfg &t, const SweepArgs &
         case SP_BF16: return launch_cfg<__bf16>(mode, t, a, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_inject(float *field, int64_t sy, int64_t sz, const float *v, int64_t vsy,
+                         int64_t vsz, int nx, int ny, int nz, const int32_t *xyz, int n,
+                         const float *amp, float scale, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int bs = 256;
+    hipLaunchKernelGGL(k_inject, dim3((n + bs - 1) / bs), dim3(bs), 0, s, field, sy, sz, v, vsy,
+                       vsz, nx, ny, nz, xyz, n, amp, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_finish(const double *G, const float *v, float *out, int64_t sy, int64_t sz,
+                              int nx, int ny, int nz, hipStream_t s) {
+    const int64_t n = (int64_t)nx * ny * nz;
+    const int bs = 256;
+    hipLaunchKernelGGL(k_grad_finish, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, s, G, v,
+                       out, sy, sz, nx, ny, nz);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum(const double *partial, int n, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(64), 0, s, partial, n, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_record(int dtype, const void *u, const float *scale, int64_t sy, int64_t sz,

@@ -42,14 +42,17 @@ class Field:
         h = lib.SP_HALO
         return self.padded()[h:-h, h:-h, h:-h]
 
+    def _as_tensor(self, a) -> torch.Tensor:
+        if not isinstance(a, torch.Tensor):
+            a = torch.as_tensor(np.ascontiguousarray(a))
+        return a.to(self.buf.device, self.tdtype)
+
     def set_interior(self, a) -> "Field":
-        t = torch.as_tensor(np.ascontiguousarray(a)).to(self.buf.device, self.tdtype)
-        self.interior().copy_(t)
+        self.interior().copy_(self._as_tensor(a))
         return self
 
     def set_padded(self, a) -> "Field":
-        t = torch.as_tensor(np.ascontiguousarray(a)).to(self.buf.device, self.tdtype)
-        self.padded().copy_(t)
+        self.padded().copy_(self._as_tensor(a))
         return self
 
     def get_interior(self) -> np.ndarray:

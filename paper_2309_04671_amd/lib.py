@@ -25,7 +25,8 @@ ERROR_NAMES = {0: "SP_OK", 1: "SP_EINVAL", 2: "SP_EUNSUPPORTED", 3: "SP_EDEVICE"
 # Every symbol include/stencil.h declares (checked by the ABI tests).
 EXPORTS = [
     "sp_grid_init", "sp_stencil_apply", "sp_wave_meta_bytes", "sp_wave_step",
-    "sp_last_error", "sp_version",
+    "sp_wave_run_states", "sp_wave_adjoint_step", "sp_grad_finish", "sp_energy_ws_bytes",
+    "sp_energy", "sp_last_error", "sp_version",
 ]
 
 
@@ -81,11 +82,20 @@ def load():
     lib.sp_wave_meta_bytes.restype = i64
     lib.sp_wave_step.argtypes = [P(sp_grid), P(sp_coeffs), d, d, P(sp_grid), vp, P(sp_wave_state), i,
                                  P(sp_sources), P(sp_receivers), vp]
+    lib.sp_wave_run_states.argtypes = [P(sp_grid), P(sp_coeffs), d, d, P(sp_grid), vp, P(vp), i64,
+                                       i, P(sp_sources), P(sp_receivers), vp]
+    lib.sp_wave_adjoint_step.argtypes = [P(sp_grid), P(sp_coeffs), d, d, P(sp_grid), vp,
+                                         P(sp_wave_state), P(vp), i, P(sp_sources),
+                                         P(sp_receivers), vp, vp]
+    lib.sp_grad_finish.argtypes = [P(sp_grid), vp, vp, vp, vp]
+    lib.sp_energy_ws_bytes.argtypes = [P(sp_grid)]
+    lib.sp_energy_ws_bytes.restype = i64
+    lib.sp_energy.argtypes = [P(sp_grid), P(sp_coeffs), d, d, P(sp_grid), vp, vp, vp, vp, vp, vp]
     lib.sp_last_error.restype = ctypes.c_char_p
     lib.sp_version.restype = ctypes.c_char_p
     for name in EXPORTS:
         fn = getattr(lib, name)
-        if name in ("sp_grid_init", "sp_stencil_apply", "sp_wave_step"):
+        if name not in ("sp_wave_meta_bytes", "sp_energy_ws_bytes", "sp_last_error", "sp_version"):
             fn.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -159,3 +169,36 @@ def sp_wave_step(g, c, dt, dx, gv, v_ptr, state, nsteps, src=None, rec=None, str
                               ctypes.c_void_p(v_ptr), ctypes.byref(state), int(nsteps),
                               ctypes.byref(src) if src is not None else None,
                               ctypes.byref(rec) if rec is not None else None, stream_ptr(stream)))
+
+
+def _ptrs(ptrs):
+    arr = (ctypes.c_void_p * len(ptrs))(*[int(p) for p in ptrs])
+    return arr
+
+
+def sp_wave_run_states(g, c, dt, dx, gv, v_ptr, states, n0, nsteps, src=None, rec=None, stream=None):
+    arr = _ptrs(states)
+    check(load().sp_wave_run_states(ctypes.byref(g), ctypes.byref(c), float(dt), float(dx),
+                                    ctypes.byref(gv), ctypes.c_void_p(v_ptr), arr, int(n0), int(nsteps),
+                                    ctypes.byref(src) if src is not None else None,
+                                    ctypes.byref(rec) if rec is not None else None, stream_ptr(stream)))
+
+
+def sp_wave_adjoint_step(g, c, dt, dx, gv, v_ptr, adj, u_hist, nsteps, src, rec, G_ptr, stream=None):
+    arr = _ptrs(u_hist)
+    check(load().sp_wave_adjoint_step(ctypes.byref(g), ctypes.byref(c), float(dt), float(dx),
+                                      ctypes.byref(gv), ctypes.c_void_p(v_ptr), ctypes.byref(adj), arr,
+                                      int(nsteps), ctypes.byref(src) if src is not None else None,
+                                      ctypes.byref(rec) if rec is not None else None,
+                                      ctypes.c_void_p(G_ptr), stream_ptr(stream)))
+
+
+def sp_grad_finish(gv, v_ptr, G_ptr, out_ptr, stream=None):
+    check(load().sp_grad_finish(ctypes.byref(gv), ctypes.c_void_p(v_ptr), ctypes.c_void_p(G_ptr),
+                                ctypes.c_void_p(out_ptr), stream_ptr(stream)))
+
+
+def sp_energy(g, c, dt, dx, gv, v_ptr, u0_ptr, u1_ptr, out_ptr, ws_ptr, stream=None):
+    check(load().sp_energy(ctypes.byref(g), ctypes.byref(c), float(dt), float(dx), ctypes.byref(gv),
+                           ctypes.c_void_p(v_ptr), ctypes.c_void_p(u0_ptr), ctypes.c_void_p(u1_ptr),
+                           ctypes.c_void_p(out_ptr), ctypes.c_void_p(ws_ptr), stream_ptr(stream)))
