@@ -228,6 +228,88 @@ int sp_energy(const sp_grid *g, const sp_coeffs *c, double dt, double dx,
               const sp_grid *gv, const float *v, const void *u0, const void *u1,
               double *out, void *ws, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Continuous-batching shot queue.
+ *
+ * Forward-modelling requests ("shots": one grid, velocity model, sources,
+ * receivers and step count each, FP32 or FP16/BF16 storage) are admitted
+ * while the queue's resident HBM budget and slot count allow, and advanced
+ * together in chunks of chunk_steps leapfrog steps: every step of a chunk
+ * is one batched kernel launch per (storage type, tile shape) covering the
+ * tiles of every resident shot, plus one batched receiver launch, and the
+ * chunk is replayed from a captured HIP graph while the set of resident
+ * shots is unchanged.  Requests that arrive while others run are admitted
+ * at the next chunk boundary as slots and memory free up.  Each shot
+ * computes exactly what sp_wave_step computes for it alone (same kernels,
+ * same per-point arithmetic), so its results do not depend on the mix.
+ * ---------------------------------------------------------------------- */
+
+#define SP_QUEUE_EAGER 1   /* launch chunks directly instead of through captured graphs */
+#define SP_QUEUE_FAKE  2   /* host logic only: no device work; chunks finish at once */
+
+#define SP_SHOT_QUEUED  0
+#define SP_SHOT_RUNNING 1
+#define SP_SHOT_DONE    2
+#define SP_SHOT_FAILED  3
+
+typedef struct {
+    void *arena;            /* DEVICE buffer owned by the caller (any pointer if SP_QUEUE_FAKE) */
+    int64_t arena_bytes;
+    int64_t budget_bytes;   /* resident shot bytes admitted at once; 0: the arena minus its control part */
+    int32_t max_slots;      /* shots resident at once (>= 1) */
+    int32_t chunk_steps;    /* steps per batched chunk (>= 1) */
+    int32_t flags;          /* SP_QUEUE_* */
+    void *stream;           /* hipStream_t on which the caller produced the shot inputs */
+} sp_queue_cfg;
+
+typedef struct {
+    int32_t nx, ny, nz;     /* interior points */
+    int32_t dtype;          /* wavefield storage: SP_F32, SP_F16 or SP_BF16 */
+    int32_t nsteps;         /* leapfrog steps (>= 1) */
+    double dt, dx;
+    sp_coeffs coeffs;
+    const float *v;         /* DEVICE interior-dense FP32 [nz][ny][nx]; copied in at admission */
+    int32_t nsrc;           /* <= SP_MAX_SOURCES */
+    int32_t src_xyz[SP_MAX_SOURCES][3];
+    const float *src_amp;   /* DEVICE FP32 [nsteps][nsrc]; read while the shot runs */
+    int32_t nrec;
+    const int32_t *rec_xyz; /* DEVICE int32 [nrec][3]; read while the shot runs */
+    float *traces;          /* DEVICE FP32 [nsteps][nrec]: row n = u^{n+1} at the receivers */
+    float *final_out;       /* optional DEVICE FP32 [nz][ny][nx]: u^nsteps (decoded) */
+} sp_shot_desc;
+
+typedef struct {
+    int32_t state;          /* SP_SHOT_* */
+    int32_t error;          /* SP_* code of a failed shot */
+    int64_t steps_done;
+    double t_submit, t_admit, t_done;   /* seconds on the host's steady clock */
+} sp_shot_status;
+
+typedef struct sp_queue sp_queue;
+
+/* Resident arena bytes of one shot (two wavefields, v, slab records), or -1
+ * for an invalid description.  Host-only. */
+int64_t sp_shot_bytes(const sp_shot_desc *d);
+
+/* Start a queue and its worker thread.  The arena must outlive the queue. */
+int sp_queue_create(const sp_queue_cfg *cfg, sp_queue **out);
+
+/* Enqueue a shot; *ticket identifies it.  SP_EBUDGET if it can never fit.
+ * The description's device buffers must stay valid until the shot is
+ * finished (v: until it is admitted). */
+int sp_submit(sp_queue *q, const sp_shot_desc *d, uint64_t *ticket);
+
+/* Status of a shot: SP_OK once it is DONE or FAILED (its traces and final
+ * field are then complete in device memory), SP_EPENDING while queued or
+ * running, SP_EINVAL for an unknown ticket. */
+int sp_poll(sp_queue *q, uint64_t ticket, sp_shot_status *st);
+
+/* Block until every shot submitted so far has finished. */
+int sp_queue_drain(sp_queue *q);
+
+/* Finish the running shots, fail the queued ones, stop the worker, free. */
+int sp_queue_destroy(sp_queue *q);
+
 /* Thread-local message for the last error on this thread ("" if none). */
 const char *sp_last_error(void);
 

@@ -12,8 +12,10 @@
 #include "internal.h"
 
 namespace {
-
 thread_local char g_err[512] = "";
+}  // namespace
+
+namespace sp {
 
 int fail(int code, const char *fmt, ...) {
     va_list ap;
@@ -27,6 +29,12 @@ int ok() {
     g_err[0] = '\0';
     return SP_OK;
 }
+
+}  // namespace sp
+
+namespace {
+using sp::fail;
+using sp::ok;
 
 int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
@@ -172,7 +180,7 @@ int64_t sp_wave_meta_bytes(const sp_grid *g) {
 
 }  // extern "C"
 
-namespace {
+namespace sp {
 
 // Validation and argument setup shared by the leapfrog entry points.
 int prep_wave(const char *who, const sp_grid *g, const sp_coeffs *c, double dt, double dx,
@@ -228,7 +236,31 @@ int prep_wave(const char *who, const sp_grid *g, const sp_coeffs *c, double dt, 
     return SP_OK;
 }
 
-}  // namespace
+void step_args(SweepArgs &a, const sp_grid *g, void *cur, void *prev, void *out, float *meta,
+               int64_t n, const float *amp, int64_t amp_stride) {
+    const int64_t eb = g->elem_bytes;
+    a.u = static_cast<char *>(cur) + g->origin * eb;
+    a.prev = static_cast<char *>(prev) + g->origin * eb;
+    a.out = static_cast<char *>(out) + g->origin * eb;
+    if (meta) {
+        const int nslab = (g->nz + SP_SLAB - 1) / SP_SLAB;
+        auto slot = [&](int64_t k) { return meta + ((k % 4 + 4) % 4) * 2 * nslab; };
+        a.meta.nslab = nslab;
+        a.meta.s_u = slot(n);
+        a.meta.a_u = reinterpret_cast<const uint32_t *>(slot(n) + nslab);
+        a.meta.s_prev = slot(n - 1);
+        a.meta.a_prev = reinterpret_cast<const uint32_t *>(slot(n - 1) + nslab);
+        a.meta.s_out = slot(n + 1);
+        a.meta.a_out = reinterpret_cast<uint32_t *>(slot(n + 1) + nslab);
+        a.meta.s_clear = slot(n + 2);
+        a.meta.a_clear = reinterpret_cast<uint32_t *>(slot(n + 2) + nslab);
+    }
+    if (a.src.n > 0) a.src.amp = amp + n * amp_stride;
+}
+
+}  // namespace sp
+
+using sp::prep_wave;
 
 extern "C" {
 
@@ -257,28 +289,11 @@ int sp_wave_step(const sp_grid *g, const sp_coeffs *c, double dt, double dx, con
     const int nslab = (g->nz + SP_SLAB - 1) / SP_SLAB;
     float *meta = static_cast<float *>(st->meta);
     auto slot_s = [&](int64_t k) { return meta + ((k % 4 + 4) % 4) * 2 * nslab; };
-    auto slot_a = [&](int64_t k) {
-        return reinterpret_cast<uint32_t *>(meta + ((k % 4 + 4) % 4) * 2 * nslab + nslab);
-    };
     for (int k = 0; k < nsteps; ++k) {
-        char *cur = static_cast<char *>(st->cur) + g->origin * eb;
         char *prev = static_cast<char *>(st->prev) + g->origin * eb;
-        a.u = cur;
-        a.prev = prev;
-        a.out = prev;
         const int64_t n = st->step;
-        if (meta) {
-            a.meta.nslab = nslab;
-            a.meta.s_u = slot_s(n);
-            a.meta.a_u = slot_a(n);
-            a.meta.s_prev = slot_s(n - 1);
-            a.meta.a_prev = slot_a(n - 1);
-            a.meta.s_out = slot_s(n + 1);
-            a.meta.a_out = slot_a(n + 1);
-            a.meta.s_clear = slot_s(n + 2);
-            a.meta.a_clear = slot_a(n + 2);
-        }
-        if (nsrc > 0) a.src.amp = src->amp + st->step * src->amp_stride;
+        sp::step_args(a, g, st->cur, st->prev, st->prev, meta, n, nsrc ? src->amp : nullptr,
+                      nsrc ? src->amp_stride : 0);
         hipError_t err = sp::launch_sweep(sp::MODE_WAVE, g->dtype, t, a, s);
         if (err == hipSuccess && nrec > 0)
             err = sp::launch_record(g->dtype, prev, meta ? slot_s(n + 1) : nullptr, a.sy, a.sz,

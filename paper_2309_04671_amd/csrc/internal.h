@@ -91,4 +91,38 @@ hipError_t launch_grad_finish(const double *G, const float *v, float *out, int64
 // *out = sum of n partials, in index order.
 hipError_t launch_sum(const double *partial, int n, double *out, hipStream_t s);
 
+// Error reporting shared by the C-ABI translation units (thread-local message).
+int fail(int code, const char *fmt, ...);
+int ok();
+// Validate the arguments common to the leapfrog calls and fill a, t.
+int prep_wave(const char *who, const sp_grid *g, const sp_coeffs *c, double dt, double dx,
+              const sp_grid *gv, const float *v, const sp_sources *src, const sp_receivers *rec,
+              SweepArgs *a, TileCfg *t);
+// Per-step pointers (fields given by allocation base), slab records and source row.
+void step_args(SweepArgs &a, const sp_grid *g, void *cur, void *prev, void *out, float *meta,
+               int64_t n, const float *amp, int64_t amp_stride);
+
+// Receiver recording of one grid in a batched launch (newest field).
+struct RecArgs {
+    const void *field;       // at interior origin, storage type of the launch
+    const float *scale;      // per-slab scales of the field (FP16/BF16) or null
+    const int32_t *xyz;      // device [n][3]
+    float *traces;           // this step's row
+    int64_t sy, sz;
+    int nx, ny, nz, n;
+};
+
+// Batched sweep: nblk blocks; block b computes tile table[b].y of the grid
+// whose arguments are args[table[b].x] (device arrays).
+hipError_t launch_sweep_batch(int mode, int dtype, const TileCfg &t, const SweepArgs *args,
+                              const int2 *table, int nblk, hipStream_t s);
+// Batched receivers: thread r records receiver rmap[r].y of grid rmap[r].x.
+hipError_t launch_record_batch(int dtype, const RecArgs *recs, const int2 *rmap, int total,
+                               hipStream_t s);
+// Interior-dense FP32 [nz][ny][nx] <-> field at interior origin.
+hipError_t launch_pack(const float *dense, float *field, int64_t sy, int64_t sz, int nx, int ny,
+                       int nz, hipStream_t s);
+hipError_t launch_unpack(int dtype, const void *field, const float *scale, float *dense,
+                         int64_t sy, int64_t sz, int nx, int ny, int nz, hipStream_t s);
+
 }  // namespace sp

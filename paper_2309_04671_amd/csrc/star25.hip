@@ -153,8 +153,7 @@ __device__ float slab_scale(const SweepArgs &a, int k) {
 //   TX: tile width in points (4 per lane), TY: tile height in rows,
 //   RY: adjacent rows per thread (register blocking in y), T: storage type.
 template <int TX, int TY, int RY, int MODE, typename T>
-__global__ void __launch_bounds__((TX / 4) * (TY / RY))
-k_star25(SweepArgs a) {
+__device__ __forceinline__ void star25_body(const SweepArgs &a, const int lin) {
     typedef Io<T> IO;
     typedef typename IO::raw raw;
     constexpr int LX = TX / 4;           // lanes per tile row
@@ -170,7 +169,6 @@ k_star25(SweepArgs a) {
     constexpr bool PW = (MODE == MODE_WAVE || MODE == MODE_GRAD || MODE == MODE_ENERGY);  // reads `prev`
     __shared__ f4v lds[2][LR][LC];
 
-    const int lin = xcd_tile(blockIdx.x, gridDim.x);
     const int tix = lin % a.tiles_x;
     const int rest = lin / a.tiles_x;
     const int tiy = rest % a.tiles_y;
@@ -475,6 +473,22 @@ k_star25(SweepArgs a) {
     }
 }
 
+template <int TX, int TY, int RY, int MODE, typename T>
+__global__ void __launch_bounds__((TX / 4) * (TY / RY))
+k_star25(SweepArgs a) {
+    star25_body<TX, TY, RY, MODE, T>(a, xcd_tile(blockIdx.x, gridDim.x));
+}
+
+// Batched form: block b computes tile table[b].y of grid table[b].x, whose
+// arguments are args[table[b].x].  The host lays the table out so that each
+// XCD receives contiguous tiles of the same grid.
+template <int TX, int TY, int RY, int MODE, typename T>
+__global__ void __launch_bounds__((TX / 4) * (TY / RY))
+k_star25_batch(const SweepArgs *__restrict__ args, const int2 *__restrict__ table) {
+    const int2 e = table[blockIdx.x];
+    star25_body<TX, TY, RY, MODE, T>(args[e.x], e.y);
+}
+
 __global__ void k_inject(float *field, int64_t sy, int64_t sz, const float *v, int64_t vsy,
                          int64_t vsz, int nx, int ny, int nz, const int32_t *xyz, int n,
                          const float *amp, float scale) {
@@ -518,6 +532,61 @@ __global__ void k_record(const T *u, const float *scale, int64_t sy, int64_t sz,
         val = Io<T>::dec1(u[(int64_t)z * sz + (int64_t)y * sy + x], s);
     }
     traces[r] = val;
+}
+
+template <typename T>
+__global__ void k_record_batch(const RecArgs *__restrict__ recs, const int2 *__restrict__ rmap,
+                               int total) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= total) return;
+    const int2 e = rmap[r];
+    const RecArgs &a = recs[e.x];
+    const int i = e.y;
+    const int x = a.xyz[3 * i], y = a.xyz[3 * i + 1], z = a.xyz[3 * i + 2];
+    float val = 0.f;
+    if (x >= 0 && x < a.nx && y >= 0 && y < a.ny && z >= 0 && z < a.nz) {
+        const float sc = a.scale ? a.scale[z >> 4] : 1.f;
+        val = Io<T>::dec1(static_cast<const T *>(a.field)[(int64_t)z * a.sz + (int64_t)y * a.sy + x], sc);
+    }
+    a.traces[i] = val;
+}
+
+__global__ void k_pack(const float *dense, float *field, int64_t sy, int64_t sz, int nx, int ny, int nz) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)nx * ny * nz) return;
+    const int x = (int)(i % nx);
+    const int64_t r = i / nx;
+    const int y = (int)(r % ny), z = (int)(r / ny);
+    field[(int64_t)z * sz + (int64_t)y * sy + x] = dense[i];
+}
+
+template <typename T>
+__global__ void k_unpack(const T *field, const float *scale, float *dense, int64_t sy, int64_t sz,
+                         int nx, int ny, int nz) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)nx * ny * nz) return;
+    const int x = (int)(i % nx);
+    const int64_t r = i / nx;
+    const int y = (int)(r % ny), z = (int)(r / ny);
+    const float sc = scale ? scale[z >> 4] : 1.f;
+    dense[i] = Io<T>::dec1(field[(int64_t)z * sz + (int64_t)y * sy + x], sc);
+}
+
+template <int TX, int TY, int RY, typename T>
+hipError_t launch_batch_t(int mode, const SweepArgs *args, const int2 *table, int nblk, hipStream_t s) {
+    const dim3 grid(nblk), block((TX / 4) * (TY / RY));
+    if (mode != MODE_WAVE) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_star25_batch<TX, TY, RY, MODE_WAVE, T>), grid, block, 0, s, args, table);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_batch_cfg(int mode, const TileCfg &t, const SweepArgs *args, const int2 *table,
+                            int nblk, hipStream_t s) {
+    if (t.tx == 256 && t.ty == 16 && t.ry == 2) return launch_batch_t<256, 16, 2, T>(mode, args, table, nblk, s);
+    if (t.tx == 128 && t.ty == 16 && t.ry == 2) return launch_batch_t<128, 16, 2, T>(mode, args, table, nblk, s);
+    if (t.tx == 64 && t.ty == 16 && t.ry == 1) return launch_batch_t<64, 16, 1, T>(mode, args, table, nblk, s);
+    return hipErrorInvalidValue;
 }
 
 template <int TX, int TY, int RY, typename T>
@@ -636,6 +705,63 @@ hipError_t launch_record(int dtype, const void *u, const float *scale, int64_t s
         case SP_BF16:
             hipLaunchKernelGGL(k_record<__bf16>, g, b, 0, s, static_cast<const __bf16 *>(u),
                                scale, sy, sz, nx, ny, nz, xyz, n, traces);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_batch(int mode, int dtype, const TileCfg &t, const SweepArgs *args,
+                              const int2 *table, int nblk, hipStream_t s) {
+    if (nblk <= 0) return hipSuccess;
+    switch (dtype) {
+        case SP_F32: return launch_batch_cfg<float>(mode, t, args, table, nblk, s);
+        case SP_F16: return launch_batch_cfg<_Float16>(mode, t, args, table, nblk, s);
+        case SP_BF16: return launch_batch_cfg<__bf16>(mode, t, args, table, nblk, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_record_batch(int dtype, const RecArgs *recs, const int2 *rmap, int total,
+                               hipStream_t s) {
+    if (total <= 0) return hipSuccess;
+    const int bs = 256;
+    const dim3 g((total + bs - 1) / bs), b(bs);
+    switch (dtype) {
+        case SP_F32: hipLaunchKernelGGL(k_record_batch<float>, g, b, 0, s, recs, rmap, total); break;
+        case SP_F16: hipLaunchKernelGGL(k_record_batch<_Float16>, g, b, 0, s, recs, rmap, total); break;
+        case SP_BF16: hipLaunchKernelGGL(k_record_batch<__bf16>, g, b, 0, s, recs, rmap, total); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(const float *dense, float *field, int64_t sy, int64_t sz, int nx, int ny,
+                       int nz, hipStream_t s) {
+    const int64_t n = (int64_t)nx * ny * nz;
+    const int bs = 256;
+    hipLaunchKernelGGL(k_pack, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, s, dense, field,
+                       sy, sz, nx, ny, nz);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack(int dtype, const void *field, const float *scale, float *dense,
+                         int64_t sy, int64_t sz, int nx, int ny, int nz, hipStream_t s) {
+    const int64_t n = (int64_t)nx * ny * nz;
+    const int bs = 256;
+    const dim3 g((unsigned)((n + bs - 1) / bs)), b(bs);
+    switch (dtype) {
+        case SP_F32:
+            hipLaunchKernelGGL(k_unpack<float>, g, b, 0, s, static_cast<const float *>(field), scale,
+                               dense, sy, sz, nx, ny, nz);
+            break;
+        case SP_F16:
+            hipLaunchKernelGGL(k_unpack<_Float16>, g, b, 0, s, static_cast<const _Float16 *>(field),
+                               scale, dense, sy, sz, nx, ny, nz);
+            break;
+        case SP_BF16:
+            hipLaunchKernelGGL(k_unpack<__bf16>, g, b, 0, s, static_cast<const __bf16 *>(field),
+                               scale, dense, sy, sz, nx, ny, nz);
             break;
         default: return hipErrorInvalidValue;
     }

@@ -26,8 +26,12 @@ ERROR_NAMES = {0: "SP_OK", 1: "SP_EINVAL", 2: "SP_EUNSUPPORTED", 3: "SP_EDEVICE"
 EXPORTS = [
     "sp_grid_init", "sp_stencil_apply", "sp_wave_meta_bytes", "sp_wave_step",
     "sp_wave_run_states", "sp_wave_adjoint_step", "sp_grad_finish", "sp_energy_ws_bytes",
-    "sp_energy", "sp_last_error", "sp_version",
+    "sp_energy", "sp_shot_bytes", "sp_queue_create", "sp_submit", "sp_poll", "sp_queue_drain",
+    "sp_queue_destroy", "sp_last_error", "sp_version",
 ]
+
+SP_QUEUE_EAGER, SP_QUEUE_FAKE = 1, 2
+SP_SHOT_QUEUED, SP_SHOT_RUNNING, SP_SHOT_DONE, SP_SHOT_FAILED = range(4)
 
 
 class SpError(RuntimeError):
@@ -63,6 +67,26 @@ class sp_receivers(ctypes.Structure):
                 ("trace_stride", ctypes.c_int64)]
 
 
+class sp_queue_cfg(ctypes.Structure):
+    _fields_ = [("arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_int64),
+                ("budget_bytes", ctypes.c_int64), ("max_slots", ctypes.c_int32),
+                ("chunk_steps", ctypes.c_int32), ("flags", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
+class sp_shot_desc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("nsteps", ctypes.c_int32), ("dt", ctypes.c_double),
+                ("dx", ctypes.c_double), ("coeffs", sp_coeffs), ("v", ctypes.c_void_p),
+                ("nsrc", ctypes.c_int32), ("src_xyz", (ctypes.c_int32 * 3) * SP_MAX_SOURCES),
+                ("src_amp", ctypes.c_void_p), ("nrec", ctypes.c_int32), ("rec_xyz", ctypes.c_void_p),
+                ("traces", ctypes.c_void_p), ("final_out", ctypes.c_void_p)]
+
+
+class sp_shot_status(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("error", ctypes.c_int32), ("steps_done", ctypes.c_int64),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -91,11 +115,19 @@ def load():
     lib.sp_energy_ws_bytes.argtypes = [P(sp_grid)]
     lib.sp_energy_ws_bytes.restype = i64
     lib.sp_energy.argtypes = [P(sp_grid), P(sp_coeffs), d, d, P(sp_grid), vp, vp, vp, vp, vp, vp]
+    lib.sp_shot_bytes.argtypes = [P(sp_shot_desc)]
+    lib.sp_shot_bytes.restype = i64
+    lib.sp_queue_create.argtypes = [P(sp_queue_cfg), P(vp)]
+    lib.sp_submit.argtypes = [vp, P(sp_shot_desc), P(ctypes.c_uint64)]
+    lib.sp_poll.argtypes = [vp, ctypes.c_uint64, P(sp_shot_status)]
+    lib.sp_queue_drain.argtypes = [vp]
+    lib.sp_queue_destroy.argtypes = [vp]
     lib.sp_last_error.restype = ctypes.c_char_p
     lib.sp_version.restype = ctypes.c_char_p
     for name in EXPORTS:
         fn = getattr(lib, name)
-        if name not in ("sp_wave_meta_bytes", "sp_energy_ws_bytes", "sp_last_error", "sp_version"):
+        if name not in ("sp_wave_meta_bytes", "sp_energy_ws_bytes", "sp_shot_bytes", "sp_last_error",
+                        "sp_version"):
             fn.restype = ctypes.c_int
     _lib = lib
     return lib
