@@ -93,9 +93,9 @@ def test_queued_fp32_shot_matches_oracle(gpu_lib):
 def test_late_requests_join_running_batch(gpu_lib):
     from paper_2309_04671_amd import lib, serve
     cl = serve.ServeClient(arena_bytes=2 << 30, max_slots=8, chunk_steps=8)
-    first = _shots(serve, lib, [(256, 256, 128, 0, 600)])[0][1]
+    first = _shots(serve, lib, [(384, 384, 256, 0, 2000)])[0][1]      # ~0.2 s of work
     cl.submit(first)
-    time.sleep(0.05)
+    time.sleep(0.02)
     late = [s for _, s in _shots(serve, lib, [(96, 96, 64, 1, 40), (64, 64, 64, 0, 30)])]
     for s in late:
         cl.submit(s)
