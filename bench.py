@@ -201,6 +201,101 @@ def leg_adjoint(torch, lib, fields, synth, n=256, nt=1000, ckpt=32):
 
 
 
+SERVE_SHAPES = [(128, 128, 128), (192, 192, 160), (256, 256, 256), (384, 384, 256)]
+
+
+def _serve_requests(torch, lib, serve, synth, n, seed0):
+    """Seeded request stream: grid uniform over the four shapes, steps
+    U{200..2000}, FP32 or FP16 storage by a fair coin, layered v and source
+    position per request (seed 1000 + id), receivers on z = 8 every 4th cell."""
+    import numpy as np
+    reqs = []
+    for i in range(n):
+        rid = seed0 + i
+        rng = np.random.default_rng(1000 + rid)
+        nx, ny, nz = SERVE_SHAPES[int(rng.integers(0, 4))]
+        nsteps = int(rng.integers(200, 2001))
+        dtype = lib.SP_F16 if rng.integers(0, 2) else lib.SP_F32
+        v = synth.layered_velocity(nx, ny, nz, 1000 + rid)
+        dt = synth.cfl_dt(v, 10.0)
+        src = synth.random_points(nx, ny, nz, 1, 5000 + rid, margin=8)
+        amp = synth.ricker(nsteps, dt, 15.0)[:, None]
+        rec = synth.receiver_plane(nx, ny, 8, 4)
+        shot = serve.Shot(v, dt, 10.0, nsteps, synth.star25_coeffs(), src, amp, rec=rec,
+                          dtype=dtype, final=False)
+        reqs.append(shot)
+    torch.cuda.synchronize()
+    return reqs
+
+
+def leg_serve(torch, lib, fields, synth, nreq=96, rho=0.8, budget_gb=200.0, slots=32, chunk=16):
+    """Served shot stream (continuous batching): capacity from a saturating
+    batch, then Poisson arrivals at offered load rho of that capacity;
+    latency = done - submit per request."""
+    import numpy as np
+    from paper_2309_04671_amd import serve
+    budget = int(budget_gb * (1 << 30))
+    arena = budget + (256 << 20)
+    cl = serve.ServeClient(arena_bytes=arena, budget_bytes=budget, max_slots=slots, chunk_steps=chunk)
+    # capacity: a saturating batch submitted at once
+    sat = _serve_requests(torch, lib, serve, synth, 24, 100000)
+    t0 = time.perf_counter()
+    for s in sat:
+        cl.submit(s)
+    cl.drain()
+    cap_s = time.perf_counter() - t0
+    capacity = sum(s.points for s in sat) / cap_s / 1e9
+    del sat
+    # Poisson stream at rho * capacity
+    reqs = _serve_requests(torch, lib, serve, synth, nreq, 0)
+    mean_pts = float(np.mean([s.points for s in reqs]))
+    rate = rho * capacity * 1e9 / mean_pts                 # requests per second
+    gaps = np.random.default_rng(7).exponential(1.0 / rate, nreq)
+    start = time.perf_counter()
+    t_arr = start + np.cumsum(gaps)
+    for s, ta in zip(reqs, t_arr):
+        d = ta - time.perf_counter()
+        if d > 0:
+            time.sleep(d)
+        cl.submit(s)
+    cl.drain()
+    lat, waits, done_t, sub_t = [], [], [], []
+    for s in reqs:
+        ok, st = cl.poll(s.ticket)
+        if not ok or st.state != lib.SP_SHOT_DONE:
+            raise RuntimeError("served shot failed: state %d error %d" % (st.state, st.error))
+        lat.append(st.t_done - st.t_submit)
+        waits.append(st.t_admit - st.t_submit)
+        done_t.append(st.t_done)
+        sub_t.append(st.t_submit)
+    makespan = max(done_t) - min(sub_t)
+    agg = sum(s.points for s in reqs) / makespan / 1e9
+    # two requests re-run alone must reproduce their traces bit for bit
+    solo_equal = True
+    small = sorted(range(nreq), key=lambda i: reqs[i].points)[:2]
+    for i in small:
+        s = reqs[i]
+        ref = s.traces.clone()
+        s.traces.zero_()
+        cl2 = serve.ServeClient(arena_bytes=4 << 30, max_slots=1, chunk_steps=chunk)
+        cl2.submit(s)
+        cl2.drain()
+        cl2.close()
+        solo_equal = solo_equal and bool(torch.equal(ref, s.traces))
+    cl.close()
+    lat = np.array(lat)
+    return {"config": "%d requests, Poisson arrivals at %.0f%% of capacity, shapes %s, steps U{200..2000}, "
+                      "FP32/FP16 50/50, budget %.0f GB, %d slots, %d-step chunks"
+                      % (nreq, rho * 100, SERVE_SHAPES, budget_gb, slots, chunk),
+            "capacity_gpts": round(capacity, 1),
+            "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
+            "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
+            "mean_admit_wait_s": round(float(np.mean(waits)), 4),
+            "aggregate_gpts": round(agg, 1), "makespan_s": round(makespan, 3),
+            "solo_equal_sampled": solo_equal}
+
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -210,7 +305,7 @@ def main():
     ap.add_argument("--nt", type=int, default=NSTEPS,
                     help="time steps per simulation (default: the workload's 500; fewer only for "
                          "profiling runs)")
-    ap.add_argument("--legs", default="storage,storage_error,adjoint",
+    ap.add_argument("--legs", default="storage,storage_error,adjoint,serve",
                     help="extra measurements after the headline run (comma list; '' for none)")
     ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
                     help="instead of the benchmark, copy a GIB-sized buffer 4 times with torch "
@@ -330,6 +425,10 @@ def main():
     if "adjoint" in legs:
         log("adjoint gradient at 256^3")
         forms["adjoint_256"] = leg_adjoint(torch, lib, fields, synth)
+    if "serve" in legs:
+        log("served shot stream")
+        torch.cuda.empty_cache()
+        forms["serve"] = leg_serve(torch, lib, fields, synth)
     if forms:
         out["forms"] = forms
     if not args.no_cpu_baseline:

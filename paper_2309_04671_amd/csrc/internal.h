@@ -66,6 +66,10 @@ struct SweepArgs {
     int tiles_x, tiles_y, zchunk, nzc;
 };
 
+// Largest z-chunk of one block for FP16/BF16 storage (its slab scales are
+// staged in LDS).
+constexpr int MAX_ZCHUNK_SCALED = 1024;
+
 // Launch configuration chosen by the host for a grid shape.
 struct TileCfg {
     int tx, ty;          // tile extent in x (points) and y (rows)

@@ -118,11 +118,9 @@ __device__ __forceinline__ int xcd_tile(int bid, int n) {
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-// Scale of plane z of a field with per-slab scales (halo planes use the
-// nearest slab).
-__device__ __forceinline__ float plane_scale(const float *s, int z, int nslab) {
-    return s[clampi(z >> 4, 0, nslab - 1)];
-}
+// Slabs one block may touch (z-chunk of at most MAX_ZCHUNK_SCALED planes plus
+// the 4-plane margins), for the FP16/BF16 scale tables in LDS.
+constexpr int MAX_BLOCK_SLABS = MAX_ZCHUNK_SCALED / SP_SLAB + 2;
 
 // Slab exponent rule: B = 8 max(|u^n| on slabs k-1..k+1, |u^{n-1}| on slab k)
 // + sum of |injections| in slab k; scale = 2^(ceil(log2 B) - 15), or 1 when
@@ -239,8 +237,36 @@ __device__ __forceinline__ void star25_body(const SweepArgs &a, const int lin) {
     const f4v zero = {0.f, 0.f, 0.f, 0.f};
     const raw rzero = IO::enc(zero, 1.f);
 
-    auto su = [&](int zz) { return IO::scaled ? plane_scale(a.meta.s_u, zz, nslab) : 1.f; };
-    auto sprev = [&](int zz) { return IO::scaled ? plane_scale(a.meta.s_prev, zz, nslab) : 1.f; };
+    // FP16/BF16: the block's slab scales (inputs, and the outputs chosen by
+    // the rule) are computed once into LDS; the plane loop reads them there
+    // instead of issuing dependent global loads that would drain the
+    // outstanding prefetches.
+    constexpr int MAXS = IO::scaled ? MAX_BLOCK_SLABS : 1;
+    __shared__ float s_in[MAXS], s_pv[MAXS], s_o[MAXS];
+    int ks = 0;
+    if constexpr (IO::scaled) {
+        ks = clampi((zb - 4) >> 4, 0, nslab - 1);
+        const int ke = clampi((ze + 3) >> 4, 0, nslab - 1);
+        for (int t = tid; t <= ke - ks; t += NT) {
+            const int k = ks + t;
+            s_in[t] = a.meta.s_u[k];
+            s_pv[t] = a.meta.s_prev[k];
+            const float so = slab_scale(a, k);
+            s_o[t] = so;
+            if (lin % (a.tiles_x * a.tiles_y) == 0 && k >= (zb >> 4) && k <= ((ze - 1) >> 4))
+                a.meta.s_out[k] = so;
+        }
+        __syncthreads();
+    }
+    auto slab_of = [&](int zz) { return clampi(zz >> 4, 0, nslab - 1) - ks; };
+    auto su = [&](int zz) {
+        if constexpr (IO::scaled) return s_in[slab_of(zz)];
+        else return 1.f;
+    };
+    auto sprev = [&](int zz) {
+        if constexpr (IO::scaled) return s_pv[slab_of(zz)];
+        else return 1.f;
+    };
 
     f4v q[RY][9];
     raw nq[RY];
@@ -284,10 +310,8 @@ __device__ __forceinline__ void star25_body(const SweepArgs &a, const int lin) {
         const int b = z & 1;
         if constexpr (IO::scaled) {
             if (z == zb || (z & (SP_SLAB - 1)) == 0) {
-                const int k = z >> 4;
-                s_out = slab_scale(a, k);
+                s_out = s_o[slab_of(z)];
                 inv_out = 1.f / s_out;
-                if (lin % (a.tiles_x * a.tiles_y) == 0 && tid == 0) a.meta.s_out[k] = s_out;
             }
         }
         const float s4 = su(z + 4), s0 = su(z);
@@ -631,24 +655,28 @@ bool tile_supported(const TileCfg &t) {
 }
 
 TileCfg choose_tiles(int nx, int ny, int nz) {
-    // Wide tiles keep the x-halo (one 128-byte line per side per row) and
-    // the y-halo rows small relative to the tile; two rows per thread share
-    // their y-neighbour reads.
+    // Widest tile that does not waste more than a quarter of its columns on
+    // the ragged x edge: wide tiles keep the x-halo (one 128-byte line per
+    // side per row) and the y-halo rows small relative to the tile, and two
+    // rows per thread share their y-neighbour reads.  Then split z until
+    // there are enough blocks for 4 waves per SIMD (256 blocks of 512 threads
+    // or 512 of 256), down to 16-plane chunks (each chunk re-reads 8 planes
+    // of u, mostly from L2).
+    static const int cand[3][3] = {{256, 16, 2}, {128, 16, 2}, {64, 16, 1}};
     TileCfg t;
-    if (nx >= 192) {
-        t.tx = 256; t.ty = 16; t.ry = 2;
-    } else if (nx >= 96) {
-        t.tx = 128; t.ty = 16; t.ry = 2;
-    } else {
-        t.tx = 64; t.ty = 16; t.ry = 1;
+    for (int c = 0; c < 3; ++c) {
+        t.tx = cand[c][0];
+        t.ty = cand[c][1];
+        t.ry = cand[c][2];
+        const int tiles_x = (nx + t.tx - 1) / t.tx;
+        if (4 * tiles_x * t.tx <= 5 * nx || c == 2) break;
     }
     const int tiles = ((nx + t.tx - 1) / t.tx) * ((ny + t.ty - 1) / t.ty);
-    // At least one block per CU; split z only when the xy tiling alone
-    // leaves the GPU underfilled (each split re-reads 8 planes of u).
-    const int want = 256;
+    const int threads = (t.tx / 4) * (t.ty / t.ry);
+    const int want = 256 * (512 / threads);
     const int chunks = (want + tiles - 1) / tiles;
     int zc = (nz + chunks - 1) / chunks;
-    if (zc < 32) zc = 32;
+    if (zc < 16) zc = 16;
     if (zc > nz) zc = nz;
     t.zchunk = zc < 1 ? 1 : zc;
     return t;
