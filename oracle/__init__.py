@@ -50,6 +50,8 @@ def _load():
     lib.ref_energy.restype = d
     lib.ref_adjoint_grad.argtypes = [i, i, i, _dp, d, d, _dp, i, i, _ip, _dp, i, _ip, _dp, _dp]
     lib.ref_adjoint_grad.restype = d
+    lib.ref_stencil_general.argtypes = [i, i, i, i, i, _dp, _dp, _dp]
+    lib.ref_stencil_general.restype = None
     lib.ref_num_threads.argtypes = []
     lib.ref_num_threads.restype = i
     _lib = lib
@@ -151,3 +153,37 @@ def adjoint_grad(coeffs, v, dt, dx, nsteps, src, amp, rec, obs):
                                  _p(v), int(nsteps), len(src), _p(src, _ip), _p(amp),
                                  len(rec), _p(rec, _ip), _p(obs), _p(g))
     return J, g
+
+
+def stencil_general(u, w, ndim: int, sweeps: int = 1) -> np.ndarray:
+    """Stencil-suite kernel (Sec. 6 accuracy study; Eq. 3 generalised to
+    star/box shapes of radius r in 2D or 3D): ``sweeps`` applications of
+        out(p) = sum_k w[k] * in(p + k),  k over [-r, r]^ndim,
+    each reading a zero frame around the interior (a fresh zero frame per
+    sweep, as the ping-pong grids of the paper's listing keep their halo).
+
+    u: interior array (nz, ny, nx) (or (ny, nx) for ndim 2; a 3D array with
+    ndim 2 holds independent planes).  w: (2r+1,)*ndim weights, x fastest,
+    w[..., r + dy, r + dx] the weight of offset (dx, dy).  Returns the
+    interior FP64 result of the last sweep.
+    """
+    lib = _load()
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    r = (w.shape[0] - 1) // 2
+    assert w.shape == (2 * r + 1,) * ndim and 1 <= r <= HALO and ndim in (2, 3)
+    a = np.asarray(u, dtype=np.float64)
+    flat2d = a.ndim == 2
+    if flat2d:
+        a = a[None]
+    assert a.ndim == 3
+    nz, ny, nx = a.shape
+    hz = HALO if ndim == 3 else 0
+    shp = (nz + 2 * hz, ny + 2 * HALO, nx + 2 * HALO)
+    cur = np.zeros(shp)
+    cur[hz:hz + nz, HALO:-HALO, HALO:-HALO] = a
+    for _ in range(sweeps):
+        nxt = np.zeros(shp)
+        lib.ref_stencil_general(nx, ny, nz, ndim, r, _p(w), _p(cur), _p(nxt))
+        cur = nxt
+    out = cur[hz:hz + nz, HALO:-HALO, HALO:-HALO].copy()
+    return out[0] if flat2d else out

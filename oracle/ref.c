@@ -273,3 +273,42 @@ int ref_num_threads(void)
     return 1;
 #endif
 }
+
+/*
+ * Stencil suite of the paper's accuracy study (Sec. 6, the star/box kernels
+ * of radius 1..4 in 2D and 3D; Eq. 3's 25-point star is star3d4r with
+ * symmetric weights).  Plain definition, for every interior point:
+ *     out(x, y, z) = sum over offsets (dz, dy, dx) in [-r, r]^ndim of
+ *                    w[dz][dy][dx] * in(x + dx, y + dy, z + dz),
+ * with w a dense (2r+1)^ndim array, x offset fastest (index
+ * ((dz + r) * (2r+1) + (dy + r)) * (2r+1) + (dx + r); dz absent for ndim 2).
+ * Star kernels are the members whose off-axis weights are zero.  For ndim 2
+ * every z-plane is an independent 2D grid.
+ *
+ * Layout here: (nz + 2 hz) x (ny + 8) x (nx + 8) values, x fastest, with a
+ * 4-cell xy frame and a z frame of hz = 4 planes for ndim 3, none for
+ * ndim 2.  The frame is read, never written.
+ */
+void ref_stencil_general(int nx, int ny, int nz, int ndim, int r, const double *w,
+                         const double *in, double *out)
+{
+    const int hz = ndim == 3 ? H : 0;
+    const int64_t px = nx + 2 * H, py = ny + 2 * H;
+    const int n = 2 * r + 1;
+    const int rz = ndim == 3 ? r : 0;
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                double s = 0.0;
+                for (int dz = -rz; dz <= rz; ++dz)
+                    for (int dy = -r; dy <= r; ++dy)
+                        for (int dx = -r; dx <= r; ++dx) {
+                            const int64_t wi = ((int64_t)(dz + rz) * n + (dy + r)) * n + (dx + r);
+                            const int64_t ui = ((int64_t)(z + dz + hz) * py + (y + dy + H)) * px +
+                                               (x + dx + H);
+                            s += w[wi] * in[ui];
+                        }
+                out[((int64_t)(z + hz) * py + (y + H)) * px + (x + H)] = s;
+            }
+}

@@ -164,3 +164,71 @@ def wave_problem(nx: int, ny: int, nz: int, nsteps: int, seed: int = 0,
         rec = np.zeros((0, 3), dtype=np.int32)
     return {"v": v, "dt": dt, "dx": dx, "src": np.asarray(src, np.int32),
             "amp": amp, "rec": np.asarray(rec, np.int32), "nsteps": nsteps}
+
+
+# ---------------------------------------------------------------------------
+# Stencil suite of the paper's accuracy study (Sec. 6 table of kernels): star
+# and box shapes of radius 1..4 in 2D and 3D, plus four classic Jacobi
+# kernels.  name -> (shape, ndim, radius).  The paper does not print their
+# weights; suite_weights draws seeded ones.
+SUITE = {}
+for _d in (2, 3):
+    for _r in (1, 2, 3, 4):
+        SUITE["star%dd%dr" % (_d, _r)] = ("star", _d, _r)
+for _d in (2, 3):
+    for _r in (1, 2, 3, 4):
+        SUITE["box%dd%dr" % (_d, _r)] = ("box", _d, _r)
+SUITE.update({"j2d5pt": ("star", 2, 1), "j2d9pt-gol": ("box", 2, 1),
+              "j2d9pt": ("star", 2, 2), "j3d27pt": ("box", 3, 1)})
+
+
+def stencil_support(shape: str, ndim: int, r: int) -> np.ndarray:
+    """Boolean (2r+1,)*ndim mask of the offsets a kernel of this shape uses:
+    every offset for a box, the centre and the axis lines for a star."""
+    if shape == "box":
+        return np.ones((2 * r + 1,) * ndim, dtype=bool)
+    m = np.zeros((2 * r + 1,) * ndim, dtype=bool)
+    for ax in range(ndim):
+        idx = [r] * ndim
+        idx[ax] = slice(None)
+        m[tuple(idx)] = True
+    return m
+
+
+def suite_weights(name: str, seed: int, signed: bool = False) -> np.ndarray:
+    """Seeded weights for a suite kernel: dense (2r+1,)*ndim FP64 array,
+    index [dz][dy][dx] (x fastest), zero off the kernel's support.  Default:
+    positive weights U[0.05, 1] scaled to sum 1 (an averaging kernel, so
+    repeated sweeps keep values in range); signed=True: U[-1, 1]."""
+    shape, ndim, r = SUITE[name]
+    rng = np.random.default_rng(seed)
+    m = stencil_support(shape, ndim, r)
+    if signed:
+        w = rng.uniform(-1.0, 1.0, m.shape)
+    else:
+        w = rng.uniform(0.05, 1.0, m.shape)
+    w = np.where(m, w, 0.0)
+    if not signed:
+        w /= w.sum()
+    return w
+
+
+def listing_star2d4r_weights() -> np.ndarray:
+    """The star2d4r weights of the paper's example kernel (Sec. 5 listing),
+    as a 9x9 array [dy + 4][dx + 4]; the first offset of the listing's
+    ``at(., .)`` is read as x."""
+    w = np.zeros((9, 9))
+    w[4, 4] = 0.25005
+    for d, c in zip((1, 2, 3, 4), (0.06245, 0.06255, 0.06251, 0.11111)):
+        w[4, 4 - d] = w[4, 4 + d] = c
+    for d, c in zip((1, 2, 3, 4), (0.06248, 0.06243, 0.06253, -0.22220)):
+        w[4 - d, 4] = w[4 + d, 4] = c
+    return w
+
+
+def suite_field(shape, seed: int, lo: float = 1e-4, hi: float = 1e5) -> np.ndarray:
+    """Positive values log-uniform in [lo, hi] (the accuracy study's inputs
+    span 1e-4 .. 1e5), FP32-representable."""
+    rng = np.random.default_rng(seed)
+    a = np.exp(rng.uniform(np.log(lo), np.log(hi), shape))
+    return a.astype(np.float32).astype(np.float64)
