@@ -155,7 +155,7 @@ def adjoint_grad(coeffs, v, dt, dx, nsteps, src, amp, rec, obs):
     return J, g
 
 
-def stencil_general(u, w, ndim: int, sweeps: int = 1) -> np.ndarray:
+def stencil_general(u, w, ndim: int, sweeps: int = 1, frame=None) -> np.ndarray:
     """Stencil-suite kernel (Sec. 6 accuracy study; Eq. 3 generalised to
     star/box shapes of radius r in 2D or 3D): ``sweeps`` applications of
         out(p) = sum_k w[k] * in(p + k),  k over [-r, r]^ndim,
@@ -165,7 +165,9 @@ def stencil_general(u, w, ndim: int, sweeps: int = 1) -> np.ndarray:
     u: interior array (nz, ny, nx) (or (ny, nx) for ndim 2; a 3D array with
     ndim 2 holds independent planes).  w: (2r+1,)*ndim weights, x fastest,
     w[..., r + dy, r + dx] the weight of offset (dx, dy).  Returns the
-    interior FP64 result of the last sweep.
+    interior FP64 result of the last sweep.  frame: optional padded array
+    (nz + 2*hz, ny + 8, nx + 8) (hz = 4 for ndim 3, else 0) whose frame the
+    first sweep reads instead of zeros.
     """
     lib = _load()
     w = np.ascontiguousarray(w, dtype=np.float64)
@@ -180,6 +182,8 @@ def stencil_general(u, w, ndim: int, sweeps: int = 1) -> np.ndarray:
     hz = HALO if ndim == 3 else 0
     shp = (nz + 2 * hz, ny + 2 * HALO, nx + 2 * HALO)
     cur = np.zeros(shp)
+    if frame is not None:
+        cur[...] = np.asarray(frame, dtype=np.float64).reshape(shp)
     cur[hz:hz + nz, HALO:-HALO, HALO:-HALO] = a
     for _ in range(sweeps):
         nxt = np.zeros(shp)

@@ -128,3 +128,18 @@ def test_suite_inputs_have_the_stated_support_and_range():
     assert f.min() >= 1e-4 * (1 - 1e-7) and f.max() <= 1e5 * (1 + 1e-7)
     L = synth.listing_star2d4r_weights()
     assert np.count_nonzero(L) == 17 and L[4, 0] == L[4, 8] == 0.11111 and L[0, 4] == -0.22220
+
+
+def test_frame_values_enter_like_interior_values():
+    # a field whose frame is read: same as correlating the whole padded array
+    w = synth.suite_weights("box3d2r", seed=2, signed=True)
+    rng = np.random.default_rng(9)
+    full = rng.standard_normal((6 + 8, 7 + 8, 9 + 8))
+    got = oracle.stencil_general(full[4:-4, 4:-4, 4:-4], w, 3, frame=full)
+    ref = ndi.correlate(full, w, mode="constant", cval=0.0)[4:-4, 4:-4, 4:-4]
+    assert np.allclose(got, ref, rtol=1e-13, atol=1e-13)
+    full2 = rng.standard_normal((3, 5 + 8, 11 + 8))
+    got = oracle.stencil_general(full2[:, 4:-4, 4:-4], synth.suite_weights("star2d4r", 1), 2, frame=full2)
+    for z in range(3):
+        ref = ndi.correlate(full2[z], synth.suite_weights("star2d4r", 1), mode="constant")[4:-4, 4:-4]
+        assert np.allclose(got[z], ref, rtol=1e-13, atol=1e-13)
