@@ -126,6 +126,61 @@ def leg_storage(torch, lib, fields, synth, steps=2, nt=1000, n=512):
     return out
 
 
+# FLOPs per point of the accuracy-study kernels as the paper counts them
+# (2P - 1 for P taps; the four Jacobi kernels carry one extra operation).
+SUITE_FLOPS = {"j2d5pt": 10, "j2d9pt-gol": 18, "j2d9pt": 18, "j3d27pt": 54}
+VALU_PEAK_GFLOPS = 78600.0      # FP32 FMA on all 256 CUs without packed-FP32 forms
+
+
+def leg_suite(torch, lib, fields, synth, sweeps=10):
+    """Stencil suite throughput: the 25-point sp_stencil_apply at 512^3 and
+    1024x1024x512, and every suite kernel through sp_apply (3D: 512^3; 2D:
+    one 8192^2 plane), `sweeps` ping-pong sweeps each; GPts/s, GB/s at 8 B
+    per point, GFLOP/s, and the fraction of the binding peak (HBM 8 TB/s or
+    the 78.6 TFLOP/s FP32 VALU)."""
+    import numpy as np
+    stream = torch.cuda.current_stream()
+    out = {}
+
+    def timed(g, fn):
+        a, b = fields.Field(g), fields.Field(g)
+        a.set_interior(torch.rand((g.nz, g.ny, g.nx), generator=torch.Generator().manual_seed(0)))
+        fn(g, a, b, 1)                                   # warm-up sweep
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn(g, a, b, sweeps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ok = bool(torch.isfinite(b.interior()).all())
+        return e0.elapsed_time(e1) / sweeps, ok
+
+    def record(name, g, ms, flops, ok):
+        gpts = g.nx * g.ny * g.nz / (ms / 1e3) / 1e9
+        gbs, gfl = gpts * 8, gpts * flops
+        bound = "alu" if flops * HBM_PEAK_GBS / 8 > VALU_PEAK_GFLOPS else "hbm"
+        frac = gfl / VALU_PEAK_GFLOPS if bound == "alu" else gbs / HBM_PEAK_GBS
+        out[name] = {"grid": [g.nx, g.ny, g.nz], "gpts": round(gpts, 2), "us_per_sweep": round(ms * 1e3, 1),
+                     "gbs_at_8B": round(gbs, 1), "gflops": round(gfl, 1), "flops_per_point": flops,
+                     "bound": bound, "frac": round(frac, 4), "finite": ok}
+
+    co = lib.coeffs(synth.star25_coeffs())
+    for n3 in ((512, 512, 512), (1024, 1024, 512)):
+        g = lib.grid_init(*n3)
+        ms, ok = timed(g, lambda g, a, b, k: lib.sp_stencil_apply(g, co, k, a.ptr, b.ptr, stream=stream))
+        record("apply25_%dx%dx%d" % n3, g, ms, 49, ok)
+    for name in sorted(synth.SUITE):
+        kind, ndim, r = synth.SUITE[name]
+        w = synth.suite_weights(name, 0)
+        g = lib.grid_init(512, 512, 512) if ndim == 3 else lib.grid_init_2d(8192, 8192)
+        ms, ok = timed(g, lambda g, a, b, k: lib.sp_apply(g, kind, w, a.ptr, b.ptr, k, stream=stream))
+        flops = SUITE_FLOPS.get(name, 2 * int(np.count_nonzero(w)) - 1)
+        record(name, g, ms, flops, ok)
+        torch.cuda.empty_cache()
+    out["config"] = ("%d sweeps each after one warm-up sweep; inputs U[0,1) FP32; seeded positive "
+                     "weights (sum 1)" % sweeps)
+    return out
+
+
 def leg_storage_error(torch, lib, fields, synth, n=128, nt=1000):
     """Error of each storage form against the FP64 oracle after nt steps."""
     import numpy as np
@@ -305,7 +360,14 @@ def main():
     ap.add_argument("--nt", type=int, default=NSTEPS,
                     help="time steps per simulation (default: the workload's 500; fewer only for "
                          "profiling runs)")
-    ap.add_argument("--legs", default="storage,storage_error,adjoint,serve",
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16"],
+                    help="wavefield storage of the headline run (f32 is the benchmark; the others "
+                         "only for profiling runs)")
+    ap.add_argument("--grid", default=None, metavar="NXxNYxNZ",
+                    help="override the headline grid (profiling runs only)")
+    ap.add_argument("--no-headline", action="store_true",
+                    help="skip the headline run (profiling runs of the extra legs)")
+    ap.add_argument("--legs", default="storage,storage_error,adjoint,suite,serve",
                     help="extra measurements after the headline run (comma list; '' for none)")
     ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
                     help="instead of the benchmark, copy a GIB-sized buffer 4 times with torch "
@@ -335,55 +397,58 @@ def main():
                           "bytes_written_per_launch": n, "launches": 4}))
         return
     nt = args.nt
+    nx, ny, nz = (NX, NY, NZ) if not args.grid else (int(a) for a in args.grid.split("x"))
+    sdt = {"f32": lib.SP_F32, "f16": lib.SP_F16, "bf16": lib.SP_BF16}[args.dtype]
+    if args.no_headline:
+        args.steps = 0
 
-    log("setting up %dx%dx%d" % (NX, NY, NZ))
-    g = lib.grid_init(NX, NY, NZ, lib.SP_F32)
-    vel = synth.layered_velocity(NX, NY, NZ, 0)
+    log("setting up %dx%dx%d" % (nx, ny, nz))
+    gv = lib.grid_init(nx, ny, nz, lib.SP_F32)
+    g = lib.grid_init(nx, ny, nz, sdt)
+    vel = synth.layered_velocity(nx, ny, nz, 0)
     dx = 10.0
     dt = synth.cfl_dt(vel, dx)
-    V = fields.Field(g).set_interior(vel)
+    V = fields.Field(gv).set_interior(vel)
     del vel
-    P, C = fields.Field(g), fields.Field(g)
+    ws = fields.WaveState(g)
     w = synth.ricker(nt, dt, 15.0)
     amp = torch.tensor(w[:, None], dtype=torch.float32, device=dev)
-    src = lib.make_sources([[NX // 2, NY // 2, NZ // 2]], amp.data_ptr(), 1)
+    src = lib.make_sources([[nx // 2, ny // 2, nz // 2]], amp.data_ptr(), 1)
     co = lib.coeffs(synth.star25_coeffs())
     ev = []
 
     def simulate(timed):
-        P.buf.zero_()
-        C.buf.zero_()
-        st = lib.sp_wave_state(C.ptr, P.ptr, None, 0)
+        ws.reset()
         if timed:
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-        lib.sp_wave_step(g, co, dt, dx, g, V.ptr, st, nt, src=src, stream=stream)
+        lib.sp_wave_step(g, co, dt, dx, gv, V.ptr, ws.st, nt, src=src, stream=stream)
         if timed:
             e1.record(stream)
             ev.append((e0, e1))
-        return st
 
-    for i in range(args.warmup):
+    for i in range(args.warmup if args.steps else 0):
         simulate(False)
         torch.cuda.synchronize()
         log("warmup %d done" % i)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        st = simulate(True)
+        simulate(True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     log("timed %d simulations in %.3f s" % (args.steps, wall))
-    final = (P if st.cur == P.ptr else C).interior()
-    if not bool(torch.isfinite(final).all()):
+    if args.steps and not bool(torch.isfinite(ws.cur().interior().float()).all()):
         raise RuntimeError("non-finite wavefield")
 
-    npts = NX * NY * NZ
-    gpts = npts * nt * args.steps / wall / 1e9
+    npts = nx * ny * nz
+    bpp = BYTES_PER_POINT if sdt == lib.SP_F32 else 10
+    steps_done = max(args.steps, 1)
+    gpts = npts * nt * args.steps / max(wall, 1e-9) / 1e9
     kern_ms = sum(a.elapsed_time(b) for a, b in ev)      # event pairs on the launch stream
-    launch_s = kern_ms / 1e3 / (nt * args.steps)
-    achieved = BYTES_PER_POINT * npts / launch_s / 1e9
-    traffic = measured_traffic()
+    launch_s = kern_ms / 1e3 / (nt * steps_done) if ev else float("nan")
+    achieved = bpp * npts / launch_s / 1e9 if ev else 0.0
+    traffic = measured_traffic() if (sdt == lib.SP_F32 and (nx, ny, nz) == (NX, NY, NZ)) else None
 
     out = {
         "metric": METRIC,
@@ -392,27 +457,27 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "ms_per_step": round(wall / steps_done * 1e3, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": args.dtype,
         "data": "synthetic",
-        "config": {"workload": "acoustic leapfrog, 25-point star, %dx%dx%d FP32, %d time steps, "
-                               "layered v (8 layers, seed 0), Ricker 15 Hz at centre, CFL 0.4"
-                               % (NX, NY, NZ, nt),
-                   "grid": [NX, NY, NZ], "time_steps": nt, "global_batch": 1,
+        "config": {"workload": "acoustic leapfrog, 25-point star, %dx%dx%d %s storage, %d time "
+                               "steps, layered v (8 layers, seed 0), Ricker 15 Hz at centre, CFL 0.4"
+                               % (nx, ny, nz, args.dtype.upper(), nt),
+                   "grid": [nx, ny, nz], "time_steps": nt, "global_batch": 1,
                    "step": "one full simulation"},
         "roofline": {"bound": "hbm", "kernel": "k_star25 (WAVE)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
                      "avg_launch_us": round(launch_s * 1e6, 2),
-                     "bytes_per_launch": BYTES_PER_POINT * npts},
+                     "bytes_per_launch": bpp * npts},
         "hbm_frac_of_wall": round(gpts * BYTES_PER_POINT / HBM_PEAK_GBS, 4),
         "gflops": round(gpts * FLOPS_PER_POINT, 1),
     }
-    del P, C, V
+    del ws, V
     torch.cuda.empty_cache()
     legs = [x for x in args.legs.split(",") if x]
     forms = {}
@@ -425,6 +490,9 @@ def main():
     if "adjoint" in legs:
         log("adjoint gradient at 256^3")
         forms["adjoint_256"] = leg_adjoint(torch, lib, fields, synth)
+    if "suite" in legs:
+        log("stencil suite")
+        forms["suite"] = leg_suite(torch, lib, fields, synth)
     if "serve" in legs:
         log("served shot stream")
         torch.cuda.empty_cache()

@@ -82,6 +82,14 @@ typedef struct {
 int sp_grid_init(int nx, int ny, int nz, int halo, int dtype, sp_grid *out);
 
 /*
+ * 2D grid: one plane of nx x ny interior points with the 4-cell frame in x
+ * and y only (nz = 1, planes = 1, no z halo); cell (x, y) is element
+ *     origin + y * pitch_x + x.
+ * Only the 2D stencils of sp_apply accept it.  halo must be 4.  Host-only.
+ */
+int sp_grid_init_2d(int nx, int ny, int halo, int dtype, sp_grid *out);
+
+/*
  * Stencil weights of Eq. 3 at unit spacing: centre c_xyz and c_xm, c_ym, c_zm
  * for m = 1..4.  Given in FP64; the kernels use them rounded once to FP32.
  */
@@ -100,6 +108,38 @@ typedef struct {
  */
 int sp_stencil_apply(const sp_grid *g, const sp_coeffs *c, int sweeps,
                      void *u, void *v, int *result_in, void *stream);
+
+/*
+ * Stencil suite (the star- and box-shaped kernels of radius 1..4 in 2D and 3D
+ * of the paper's accuracy study, Sec. 6; Eq. 3 is star3d4r with symmetric
+ * weights):
+ *     out(p) = sum over offsets k in [-r, r]^ndim of w[k] * u(p + k)
+ * on every interior point, reading u's halo (zero for the Dirichlet frame).
+ * w is a HOST array of (2r+1)^ndim FP64 weights, x offset fastest: the
+ * weight of offset (dx, dy, dz) is w[((dz + r) * (2r+1) + dy + r) * (2r+1)
+ * + dx + r] (no dz term for ndim 2).  A star's weights must be zero off the
+ * three (two) axis lines through the centre.  The kernels use the weights
+ * rounded once to FP32.
+ */
+#define SP_STAR 0
+#define SP_BOX  1
+typedef struct {
+    int32_t shape;          /* SP_STAR or SP_BOX */
+    int32_t ndim;           /* 2 or 3 */
+    int32_t radius;         /* 1 .. 4 (<= the halo) */
+    const double *w;        /* HOST weights, see above */
+} sp_stencil;
+
+/*
+ * sp_apply -- `sweeps` sweeps of a suite stencil on FP32 grids, ping-ponging
+ * u and v exactly like sp_stencil_apply (*result_in: 1 if the result is in
+ * v, 0 if in u; HOST int).  ndim 3 needs a 3D grid (sp_grid_init); ndim 2
+ * takes a 2D grid (sp_grid_init_2d) or a 3D grid, whose interior planes are
+ * then independent 2D grids.  u and v: allocations of g->bytes, distinct,
+ * 16-byte aligned.  SP_EINVAL for a bad shape, radius, weight array or grid.
+ */
+int sp_apply(const sp_grid *g, const sp_stencil *s, int sweeps, void *u, void *v,
+             int *result_in, void *stream);
 
 /*
  * Wavefield state of the leapfrog.  cur = u^n, prev = u^{n-1}; a step writes

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -40,10 +41,16 @@ int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
 bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
-int check_grid(const sp_grid *g, const char *what) {
+// A descriptor is valid if it equals what sp_grid_init (or, where 2D grids
+// are accepted, sp_grid_init_2d) makes of its own dimensions.
+int check_grid(const sp_grid *g, const char *what, bool allow_2d = false) {
     if (!g) return fail(SP_EINVAL, "%s: grid descriptor is NULL", what);
     sp_grid ref;
-    if (sp_grid_init(g->nx, g->ny, g->nz, g->halo, g->dtype, &ref) != SP_OK)
+    const bool flat = g->planes == 1;
+    if (flat && !allow_2d) return fail(SP_EINVAL, "%s: 2D grids are not accepted here", what);
+    const int rc = flat ? sp_grid_init_2d(g->nx, g->ny, g->halo, g->dtype, &ref)
+                        : sp_grid_init(g->nx, g->ny, g->nz, g->halo, g->dtype, &ref);
+    if (rc != SP_OK)
         return fail(SP_EINVAL, "%s: invalid grid descriptor (%s)", what, sp_last_error());
     if (std::memcmp(&ref, g, sizeof ref) != 0)
         return fail(SP_EINVAL, "%s: grid descriptor was not produced by sp_grid_init", what);
@@ -136,6 +143,67 @@ int sp_grid_init(int nx, int ny, int nz, int halo, int dtype, sp_grid *out) {
     g.elems = g.planes * g.pitch_y * g.pitch_x + g.pitch_x;
     g.bytes = round_up(g.elems * eb, 256);
     *out = g;
+    return ok();
+}
+
+int sp_grid_init_2d(int nx, int ny, int halo, int dtype, sp_grid *out) {
+    if (int e = sp_grid_init(nx, ny, 1, halo, dtype, out)) return e;
+    sp_grid &g = *out;
+    g.planes = 1;
+    g.origin = (int64_t)SP_HALO * g.pitch_x + 128 / g.elem_bytes;
+    g.elems = g.pitch_y * g.pitch_x + g.pitch_x;
+    g.bytes = round_up(g.elems * g.elem_bytes, 256);
+    return ok();
+}
+
+int sp_apply(const sp_grid *g, const sp_stencil *st, int sweeps, void *u, void *v, int *result_in,
+             void *stream) {
+    const char *who = "sp_apply";
+    if (int e = check_grid(g, who, true)) return e;
+    if (g->dtype != SP_F32) return fail(SP_EUNSUPPORTED, "%s: FP32 grids only", who);
+    if (!st || !st->w || !u || !v || !result_in) return fail(SP_EINVAL, "%s: NULL argument", who);
+    if (st->shape != SP_STAR && st->shape != SP_BOX)
+        return fail(SP_EINVAL, "%s: unknown stencil shape %d", who, st->shape);
+    if (st->ndim != 2 && st->ndim != 3) return fail(SP_EINVAL, "%s: ndim must be 2 or 3", who);
+    if (st->radius < 1 || st->radius > SP_HALO)
+        return fail(SP_EINVAL, "%s: radius must be 1..%d, got %d", who, SP_HALO, st->radius);
+    if (st->ndim == 3 && g->planes == 1) return fail(SP_EINVAL, "%s: a 3D stencil needs a 3D grid", who);
+    if (sweeps < 0) return fail(SP_EINVAL, "%s: sweeps < 0", who);
+    if (!aligned16(u) || !aligned16(v)) return fail(SP_EINVAL, "%s: pointers must be 16-byte aligned", who);
+    if (overlaps(u, v, g->bytes)) return fail(SP_EINVAL, "%s: u and v overlap", who);
+    if (g->pitch_x * g->pitch_y >= ((int64_t)1 << 31))
+        return fail(SP_EUNSUPPORTED, "%s: planes of 2^31 or more elements", who);
+    const int r = st->radius, D = 2 * r + 1, n = st->ndim == 3 ? D * D * D : D * D;
+    float w[9 * 9 * 9];
+    for (int i = 0; i < n; ++i) {
+        const double x = st->w[i];
+        if (!std::isfinite(x)) return fail(SP_EINVAL, "%s: weight %d is not finite", who, i);
+        int k = i, dx = k % D - r, dy, dz = 0;
+        k /= D;
+        dy = k % D - r;
+        if (st->ndim == 3) dz = k / D - r;
+        const int off_axis = (dx != 0) + (dy != 0) + (dz != 0) > 1;
+        if (st->shape == SP_STAR && off_axis && x != 0.0)
+            return fail(SP_EINVAL, "%s: star weights must be zero off the axes (index %d)", who, i);
+        w[i] = (float)x;
+    }
+    sp::SuiteArgs a;
+    a.nx = g->nx;
+    a.ny = g->ny;
+    a.nz = g->nz;
+    a.sy = g->pitch_x;
+    a.sz = g->pitch_x * g->pitch_y;
+    float *bufs[2] = {static_cast<float *>(u) + g->origin, static_cast<float *>(v) + g->origin};
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int in = 0;
+    for (int k = 0; k < sweeps; ++k) {
+        a.u = bufs[in];
+        a.out = bufs[1 - in];
+        hipError_t err = sp::launch_suite(st->shape, st->ndim, r, w, a, s);
+        if (err != hipSuccess) return fail(SP_EDEVICE, "%s: launch failed: %s", who, hipGetErrorString(err));
+        in = 1 - in;
+    }
+    *result_in = in;
     return ok();
 }
 

@@ -129,4 +129,18 @@ hipError_t launch_pack(const float *dense, float *field, int64_t sy, int64_t sz,
 hipError_t launch_unpack(int dtype, const void *field, const float *scale, float *dense,
                          int64_t sy, int64_t sz, int nx, int ny, int nz, hipStream_t s);
 
+// Stencil suite (star/box, radius 1..4, 2D/3D, arbitrary weights; FP32).
+// u and out point at interior (0, 0, 0); a 2D kernel on a grid of several
+// planes treats each interior plane as its own 2D grid.
+struct SuiteArgs {
+    const float *u;
+    float *out;
+    int nx, ny, nz;
+    int64_t sy, sz;
+};
+// w: dense (2r+1)^ndim FP32 weights, x offset fastest, zero off a star's
+// axes.  shape 0 = star, 1 = box.
+hipError_t launch_suite(int shape, int ndim, int radius, const float *w, const SuiteArgs &a,
+                        hipStream_t s);
+
 }  // namespace sp

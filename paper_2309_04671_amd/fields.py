@@ -29,18 +29,24 @@ class Field:
     def ptr(self) -> int:
         return self.buf.data_ptr()
 
+    @property
+    def hz(self) -> int:
+        """z frame width: 4, or 0 for a 2D grid (one plane, no z halo)."""
+        return 0 if self.grid.planes == 1 else lib.SP_HALO
+
     def padded(self) -> torch.Tensor:
-        """View of shape (nz+8, ny+8, nx+8) over halo and interior."""
+        """View of shape (nz+8, ny+8, nx+8) over halo and interior
+        ((1, ny+8, nx+8) for a 2D grid)."""
         g = self.grid
-        h = lib.SP_HALO
+        h, hz = lib.SP_HALO, self.hz
         flat = self.buf.view(self.tdtype)
         sy, sz = g.pitch_x, g.pitch_x * g.pitch_y
-        off = g.origin - h * sz - h * sy - h
-        return torch.as_strided(flat, (g.nz + 2 * h, g.ny + 2 * h, g.nx + 2 * h), (sz, sy, 1), off)
+        off = g.origin - hz * sz - h * sy - h
+        return torch.as_strided(flat, (g.nz + 2 * hz, g.ny + 2 * h, g.nx + 2 * h), (sz, sy, 1), off)
 
     def interior(self) -> torch.Tensor:
-        h = lib.SP_HALO
-        return self.padded()[h:-h, h:-h, h:-h]
+        h, hz = lib.SP_HALO, self.hz
+        return self.padded()[hz:hz + self.grid.nz, h:-h, h:-h]
 
     def _as_tensor(self, a) -> torch.Tensor:
         if not isinstance(a, torch.Tensor):

@@ -24,7 +24,7 @@ ERROR_NAMES = {0: "SP_OK", 1: "SP_EINVAL", 2: "SP_EUNSUPPORTED", 3: "SP_EDEVICE"
 
 # Every symbol include/stencil.h declares (checked by the ABI tests).
 EXPORTS = [
-    "sp_grid_init", "sp_stencil_apply", "sp_wave_meta_bytes", "sp_wave_step",
+    "sp_grid_init", "sp_grid_init_2d", "sp_stencil_apply", "sp_apply", "sp_wave_meta_bytes", "sp_wave_step",
     "sp_wave_run_states", "sp_wave_adjoint_step", "sp_grad_finish", "sp_energy_ws_bytes",
     "sp_energy", "sp_shot_bytes", "sp_queue_create", "sp_submit", "sp_poll", "sp_queue_drain",
     "sp_queue_destroy", "sp_last_error", "sp_version",
@@ -50,6 +50,14 @@ class sp_grid(ctypes.Structure):
 class sp_coeffs(ctypes.Structure):
     _fields_ = [("center", ctypes.c_double), ("ax", ctypes.c_double * 4),
                 ("ay", ctypes.c_double * 4), ("az", ctypes.c_double * 4)]
+
+
+class sp_stencil(ctypes.Structure):
+    _fields_ = [("shape", ctypes.c_int32), ("ndim", ctypes.c_int32), ("radius", ctypes.c_int32),
+                ("w", ctypes.POINTER(ctypes.c_double))]
+
+
+SP_STAR, SP_BOX = 0, 1
 
 
 class sp_wave_state(ctypes.Structure):
@@ -102,6 +110,8 @@ def load():
     vp, i, d, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int64
     lib.sp_grid_init.argtypes = [i, i, i, i, i, P(sp_grid)]
     lib.sp_stencil_apply.argtypes = [P(sp_grid), P(sp_coeffs), i, vp, vp, P(ctypes.c_int), vp]
+    lib.sp_grid_init_2d.argtypes = [i, i, i, i, P(sp_grid)]
+    lib.sp_apply.argtypes = [P(sp_grid), P(sp_stencil), i, vp, vp, P(ctypes.c_int), vp]
     lib.sp_wave_meta_bytes.argtypes = [P(sp_grid)]
     lib.sp_wave_meta_bytes.restype = i64
     lib.sp_wave_step.argtypes = [P(sp_grid), P(sp_coeffs), d, d, P(sp_grid), vp, P(sp_wave_state), i,
@@ -149,6 +159,12 @@ def grid_init(nx, ny, nz, dtype=SP_F32, halo=SP_HALO) -> sp_grid:
     return g
 
 
+def grid_init_2d(nx, ny, dtype=SP_F32, halo=SP_HALO) -> sp_grid:
+    g = sp_grid()
+    check(load().sp_grid_init_2d(nx, ny, halo, dtype, ctypes.byref(g)))
+    return g
+
+
 def coeffs(d) -> sp_coeffs:
     """Build sp_coeffs from {'center', 'ax', 'ay', 'az'}."""
     c = sp_coeffs()
@@ -171,6 +187,23 @@ def sp_stencil_apply(g, c, sweeps, u, v, stream=None) -> int:
     out = ctypes.c_int(-1)
     check(load().sp_stencil_apply(ctypes.byref(g), ctypes.byref(c), int(sweeps), ctypes.c_void_p(u),
                                   ctypes.c_void_p(v), ctypes.byref(out), stream_ptr(stream)))
+    return out.value
+
+
+def sp_apply(g, shape, w, u, v, sweeps=1, stream=None) -> int:
+    """Suite stencil: shape "star"/"box" (or SP_STAR/SP_BOX); w: array of
+    shape (2r+1,)*ndim, x offset last.  u, v: device pointers (int).
+    Returns result_in."""
+    import numpy as np
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    st = sp_stencil()
+    st.shape = {"star": SP_STAR, "box": SP_BOX}.get(shape, shape)
+    st.ndim = w.ndim
+    st.radius = (w.shape[0] - 1) // 2
+    st.w = w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    out = ctypes.c_int(-1)
+    check(load().sp_apply(ctypes.byref(g), ctypes.byref(st), int(sweeps), ctypes.c_void_p(u),
+                          ctypes.c_void_p(v), ctypes.byref(out), stream_ptr(stream)))
     return out.value
 
 

@@ -134,3 +134,69 @@ def test_unknown_tile_override_is_rejected(monkeypatch):
     rc = L.sp_stencil_apply(ctypes.byref(g), ctypes.byref(c), 1, ctypes.c_void_p(1 << 30),
                             ctypes.c_void_p(1 << 40), ctypes.byref(out), None)
     assert rc == lib.SP_EINVAL and "not compiled" in lib.last_error()
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (70, 37), (8192, 8192), (1000, 1000)])
+def test_grid_2d_layout(shape):
+    nx, ny = shape
+    g = lib.grid_init_2d(nx, ny)
+    g3 = lib.grid_init(nx, ny, 1)
+    assert g.nz == 1 and g.planes == 1 and g.halo == 4
+    assert g.pitch_x == g3.pitch_x and g.pitch_y == ny + 8
+    assert (g.origin * 4) % 128 == 0
+    sy = g.pitch_x
+    first = g.origin - 4 * sy - 4
+    last = g.origin + (ny + 3) * sy + (nx + 3)
+    assert first >= 0 and last < g.elems and g.elems * 4 <= g.bytes and g.bytes % 256 == 0
+    assert g.bytes < g3.bytes
+
+
+def _stencil(shape, ndim, r, w=None):
+    import numpy as np
+    w = np.ones((2 * r + 1,) * ndim) if w is None else w
+    st = lib.sp_stencil()
+    st.shape, st.ndim, st.radius = shape, ndim, r
+    st.w = w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return st, w
+
+
+def test_suite_apply_validates_before_launch():
+    import numpy as np
+    L = lib.load()
+    g3, g2 = lib.grid_init(16, 16, 16), lib.grid_init_2d(16, 16)
+    out = ctypes.c_int()
+    U, V = ctypes.c_void_p(1 << 30), ctypes.c_void_p(1 << 40)
+
+    def call(g, st, sweeps=1, u=U, v=V):
+        return L.sp_apply(ctypes.byref(g), ctypes.byref(st), sweeps, u, v, ctypes.byref(out), None)
+
+    box, wb = _stencil(lib.SP_BOX, 3, 2)
+    # a star with an off-axis weight
+    ws = np.zeros((5, 5, 5))
+    ws[2, 2, :] = 1
+    ws[0, 0, 0] = 0.5
+    st, _ = _stencil(lib.SP_STAR, 3, 2, ws)
+    assert call(g3, st) == lib.SP_EINVAL and "off the axes" in lib.last_error()
+    for shape, ndim, r in ((5, 3, 2), (lib.SP_BOX, 4, 2), (lib.SP_BOX, 3, 0), (lib.SP_BOX, 3, 5)):
+        bad, _ = _stencil(shape, ndim, r, np.ones(9 ** 3))
+        assert call(g3, bad) == lib.SP_EINVAL
+    nan = np.ones((5, 5, 5))
+    nan[1, 2, 3] = np.nan
+    bad, _ = _stencil(lib.SP_BOX, 3, 2, nan)
+    assert call(g3, bad) == lib.SP_EINVAL and "finite" in lib.last_error()
+    # 3D stencil on a 2D grid; 2D grids elsewhere in the library
+    assert call(g2, box) == lib.SP_EINVAL and "3D grid" in lib.last_error()
+    c = lib.coeffs({"center": -1, "ax": [0] * 4, "ay": [0] * 4, "az": [0] * 4})
+    assert L.sp_stencil_apply(ctypes.byref(g2), ctypes.byref(c), 1, U, V, ctypes.byref(out),
+                              None) == lib.SP_EINVAL
+    # aliasing, alignment, dtype, sweeps, forged descriptor
+    assert call(g3, box, u=ctypes.c_void_p(4096), v=ctypes.c_void_p(4096 + 256)) == lib.SP_EINVAL
+    assert call(g3, box, u=ctypes.c_void_p(4100)) == lib.SP_EINVAL
+    assert call(g3, box, sweeps=-1) == lib.SP_EINVAL
+    h = lib.grid_init(16, 16, 16, lib.SP_F16)
+    assert call(h, box) == lib.SP_EUNSUPPORTED
+    forged = lib.grid_init_2d(16, 16)
+    forged.origin += 1
+    assert call(forged, box) == lib.SP_EINVAL
+    # sweeps = 0 is a no-op that launches nothing
+    assert call(g3, box, sweeps=0) == lib.SP_OK and out.value == 0
