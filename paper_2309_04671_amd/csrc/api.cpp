@@ -84,7 +84,7 @@ void fill_tiling(sp::SweepArgs &a, const sp::TileCfg &t) {
 // tuning.  Returns false (with the error set) for a configuration that is
 // not compiled in.
 bool tiles_for(const sp_grid *g, sp::TileCfg *out, const char *who) {
-    sp::TileCfg t = sp::choose_tiles(g->nx, g->ny, g->nz);
+    sp::TileCfg t = sp::choose_tiles(g->nx, g->ny, g->nz, g->dtype);
     // Optional override for tuning: SP_TILE=TXxTYxRY[xZC]
     if (const char *e = std::getenv("SP_TILE")) {
         int tx = 0, ty = 0, ry = 0, zc = 0;

@@ -77,7 +77,9 @@ struct TileCfg {
     int zchunk;          // planes per block
 };
 
-TileCfg choose_tiles(int nx, int ny, int nz);
+TileCfg choose_tiles(int nx, int ny, int nz, int dtype);
+// Configurations the batched (multi-grid) sweep is compiled for.
+bool batch_supported(const TileCfg &t);
 bool tile_supported(const TileCfg &t);
 hipError_t launch_sweep(int mode, int dtype, const TileCfg &t, const SweepArgs &a, hipStream_t s);
 // Record u at receiver points (decoding with per-slab scales if `scale`).

@@ -514,8 +514,9 @@ int sp_submit(sp_queue *q, const sp_shot_desc *d, uint64_t *ticket) {
                               d->nrec ? &rec : nullptr, &s.base, &s.tile))
         return e;
     s.nblk = s.base.tiles_x * s.base.tiles_y * s.base.nzc;
-    if (s.tile.tx != 256 && s.tile.tx != 128 && !(s.tile.tx == 64 && s.tile.ty == 16 && s.tile.ry == 1))
-        return fail(SP_EUNSUPPORTED, "sp_submit: tile configuration not batched");
+    if (!sp::batch_supported(s.tile))
+        return fail(SP_EUNSUPPORTED, "sp_submit: tile configuration %dx%dx%d is not batched",
+                    s.tile.tx, s.tile.ty, s.tile.ry);
     s.bytes = shot_bytes(s.g, s.gv);
     {
         std::vector<const Shot *> one{&s};

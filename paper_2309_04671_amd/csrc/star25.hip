@@ -30,6 +30,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "internal.h"
 
 namespace sp {
@@ -147,11 +149,285 @@ __device__ float slab_scale(const SweepArgs &a, int k) {
     return ldexpf(1.f, e);
 }
 
+// Leapfrog step with FP16 storage.  The register queue and the LDS plane keep
+// the stored half values (two per VGPR) instead of decoded FP32 values, and
+// every tap is one mixed-precision FMA (half operand, FP32 coefficient and
+// accumulator) whose coefficient already carries the slab scale of the
+// tap's plane: scales are powers of two, so coefficient x scale is exact and
+// no separate decode is needed.  Same tiles, halo mapping, slab records and
+// rounding as the generic body; about half the queue and LDS footprint.
+template <int TX, int TY, int RY>
+__device__ __forceinline__ void star25_wave_h(const SweepArgs &a, const int lin) {
+    typedef Io<_Float16> IO;
+    typedef IO::raw raw;
+    constexpr int LX = TX / 4;
+    constexpr int NT = LX * (TY / RY);
+    constexpr int LC = LX + 2;
+    constexpr int LR = TY + 8;
+    constexpr int HY = 8 * LX;
+    constexpr int HC = HY + 2 * TY;
+    constexpr int HPT = (HC + NT - 1) / NT;
+    static_assert(TY % RY == 0, "RY must divide TY");
+    __shared__ raw lds[2][LR][LC];
+
+    const int tix = lin % a.tiles_x;
+    const int rest = lin / a.tiles_x;
+    const int tiy = rest % a.tiles_y;
+    const int zc = rest / a.tiles_y;
+    const int x0 = tix * TX, y0 = tiy * TY;
+    const int zb = zc * a.zchunk;
+    const int ze = min(a.nz, zb + a.zchunk);
+
+    const int tid = threadIdx.x;
+    const int lx = tid % LX, ly = tid / LX;
+    const int x = x0 + 4 * lx;
+    const int ybase = y0 + ly * RY;
+    const int64_t sz = a.sz;
+    const _Float16 *u = static_cast<const _Float16 *>(a.u);
+    const _Float16 *uprev = static_cast<const _Float16 *>(a.prev);
+    _Float16 *out = static_cast<_Float16 *>(a.out);
+    const int nslab = a.meta.nslab;
+
+    if (lin == 0)
+        for (int i = tid; i < nslab; i += NT) {
+            a.meta.s_clear[i] = 0.f;
+            a.meta.a_clear[i] = 0u;
+        }
+
+    bool ld_ok[RY], st_ok[RY];
+    int64_t own[RY], vown[RY];
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+        const int y = ybase + j;
+        ld_ok[j] = (y < a.ny + 4) && (x < a.nx + 4);
+        st_ok[j] = (y < a.ny) && (x < a.nx);
+        own[j] = (int64_t)y * a.sy + x;
+        vown[j] = (int64_t)y * a.vsy + x;
+    }
+
+    int hrow[HPT], hchk[HPT];
+    bool h_ok[HPT];
+    int64_t hoff[HPT];
+#pragma unroll
+    for (int j = 0; j < HPT; ++j) {
+        const int k = tid + j * NT;
+        int dy = 0, dx = 0;
+        hrow[j] = 0;
+        hchk[j] = 0;
+        if (k < HY) {
+            const int rr = k / LX, cc = k % LX;
+            dy = rr < 4 ? rr - 4 : TY + rr - 4;
+            dx = 4 * cc;
+            hrow[j] = dy + 4;
+            hchk[j] = cc + 1;
+        } else if (k < HC) {
+            const int kk = k - HY, rr = kk >> 1, side = kk & 1;
+            dy = rr;
+            dx = side ? TX : -4;
+            hrow[j] = rr + 4;
+            hchk[j] = side ? LX + 1 : 0;
+        }
+        h_ok[j] = (k < HC) && (y0 + dy < a.ny + 4) && (x0 + dx < a.nx + 4);
+        hoff[j] = (int64_t)(y0 + dy) * a.sy + (x0 + dx);
+    }
+
+    const f4v zero = {0.f, 0.f, 0.f, 0.f};
+    const raw rzero = IO::enc(zero, 1.f);
+
+    __shared__ float s_in[MAX_BLOCK_SLABS], s_pv[MAX_BLOCK_SLABS], s_o[MAX_BLOCK_SLABS];
+    const int ks = clampi((zb - 4) >> 4, 0, nslab - 1);
+    {
+        const int ke = clampi((ze + 3) >> 4, 0, nslab - 1);
+        for (int t = tid; t <= ke - ks; t += NT) {
+            const int k = ks + t;
+            s_in[t] = a.meta.s_u[k];
+            s_pv[t] = a.meta.s_prev[k];
+            const float so = slab_scale(a, k);
+            s_o[t] = so;
+            if (lin % (a.tiles_x * a.tiles_y) == 0 && k >= (zb >> 4) && k <= ((ze - 1) >> 4))
+                a.meta.s_out[k] = so;
+        }
+        __syncthreads();
+    }
+    auto slab_of = [&](int zz) { return clampi(zz >> 4, 0, nslab - 1) - ks; };
+    auto su = [&](int zz) { return s_in[slab_of(zz)]; };
+
+    raw q[RY][9];
+    raw nq[RY];
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int zz = zb - 4 + i;
+            q[j][i] = ld_ok[j] ? IO::ld(u + (int64_t)zz * sz + own[j]) : rzero;
+        }
+        nq[j] = ld_ok[j] ? IO::ld(u + (int64_t)(zb + 4) * sz + own[j]) : rzero;
+    }
+    raw hv[HPT];
+#pragma unroll
+    for (int j = 0; j < HPT; ++j) hv[j] = h_ok[j] ? IO::ld(u + (int64_t)zb * sz + hoff[j]) : rzero;
+
+    raw pp[RY];
+    f4v vv[RY];
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+        pp[j] = rzero;
+        vv[j] = zero;
+        if (st_ok[j]) {
+            pp[j] = IO::ld_nt(uprev + (int64_t)zb * sz + own[j]);
+            vv[j] = ld4_nt(a.v + (int64_t)zb * a.vsz + vown[j]);
+        }
+    }
+
+    const StarCoef &c = a.c;
+    float s_out = 1.f, inv_out = 1.f;
+    float tmax = 0.f;
+
+    for (int z = zb; z < ze; ++z) {
+        const int b = z & 1;
+        if (z == zb || (z & (SP_SLAB - 1)) == 0) {
+            s_out = s_o[slab_of(z)];
+            inv_out = 1.f / s_out;
+        }
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            q[j][8] = nq[j];
+            lds[b][ly * RY + j + 4][lx + 1] = q[j][4];
+        }
+#pragma unroll
+        for (int j = 0; j < HPT; ++j)
+            if (tid + j * NT < HC) lds[b][hrow[j]][hchk[j]] = hv[j];
+
+        raw pp_n[RY];
+        f4v vv_n[RY];
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            pp_n[j] = rzero;
+            vv_n[j] = zero;
+        }
+        if (z + 1 < ze) {
+#pragma unroll
+            for (int j = 0; j < RY; ++j)
+                nq[j] = ld_ok[j] ? IO::ld(u + (int64_t)(z + 5) * sz + own[j]) : rzero;
+#pragma unroll
+            for (int j = 0; j < HPT; ++j)
+                hv[j] = h_ok[j] ? IO::ld(u + (int64_t)(z + 1) * sz + hoff[j]) : rzero;
+#pragma unroll
+            for (int j = 0; j < RY; ++j)
+                if (st_ok[j]) {
+                    pp_n[j] = IO::ld_nt(uprev + (int64_t)(z + 1) * sz + own[j]);
+                    vv_n[j] = ld4_nt(a.v + (int64_t)(z + 1) * a.vsz + vown[j]);
+                }
+        }
+
+        lds_barrier();
+
+        raw yrow[RY + 8];
+#pragma unroll
+        for (int d = -4; d < RY + 4; ++d)
+            yrow[d + 4] = (d >= 0 && d < RY) ? q[d][4] : lds[b][ly * RY + d + 4][lx + 1];
+
+        // FP32 coefficients of this plane's taps, each times the slab scale
+        // of the plane the tap reads (exact: scales are powers of two)
+        const float s0 = su(z);
+        const float c0s = c.c0 * s0, two_s = 2.f * s0, nsp = -s_pv[slab_of(z)];
+        float czp[4], czm[4], cys[4], cxs[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            czp[r] = c.cz[r] * su(z + r + 1);
+            czm[r] = c.cz[r] * su(z - r - 1);
+            cys[r] = c.cy[r] * s0;
+            cxs[r] = c.cx[r] * s0;
+        }
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            const raw ctr = q[j][4];
+            const raw L = lds[b][ly * RY + j + 4][lx], R = lds[b][ly * RY + j + 4][lx + 2];
+            const _Float16 w[12] = {L.x, L.y, L.z, L.w, ctr.x, ctr.y, ctr.z, ctr.w, R.x, R.y, R.z, R.w};
+            f4v acc;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                float o = c0s * (float)ctr[i];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    o = fmaf(czp[r], (float)q[j][5 + r][i], o);
+                    o = fmaf(czm[r], (float)q[j][3 - r][i], o);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    o = fmaf(cys[r], (float)yrow[j + 5 + r][i], o);
+                    o = fmaf(cys[r], (float)yrow[j + 3 - r][i], o);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    o = fmaf(cxs[r], (float)w[5 + i + r], o);
+                    o = fmaf(cxs[r], (float)w[3 + i - r], o);
+                }
+                acc[i] = o;
+            }
+            const f4v m = vv[j] * vv[j] * a.m_scale;
+            f4v res;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float t = fmaf(two_s, (float)ctr[i], nsp * (float)pp[j][i]);
+                res[i] = fmaf(m[i], acc[i], t);
+            }
+            const int y = ybase + j;
+            for (int s = 0; s < a.src.n; ++s) {
+                if (a.src.z[s] == z && a.src.y[s] == y) {
+                    const int d = a.src.x[s] - x;
+                    if (d >= 0 && d < 4) {
+                        const float vs = vv[j][d];
+                        res[d] += a.src.dt2 * (vs * vs) * a.src.amp[s];
+                    }
+                }
+            }
+            if (st_ok[j]) {
+                _Float16 *o = out + (int64_t)z * sz + own[j];
+                const raw enc = IO::enc(res, inv_out);
+                const f4v mg = IO::mag(enc);
+                float mm = mg.x;
+                if (x + 1 < a.nx) mm = fmaxf(mm, mg.y);
+                if (x + 2 < a.nx) mm = fmaxf(mm, mg.z);
+                if (x + 3 < a.nx) mm = fmaxf(mm, mg.w);
+                tmax = fmaxf(tmax, mm);
+                if (x + 4 <= a.nx) {
+                    IO::st_nt(o, enc);
+                } else {
+                    o[0] = enc[0];
+                    if (x + 1 < a.nx) o[1] = enc[1];
+                    if (x + 2 < a.nx) o[2] = enc[2];
+                }
+            }
+        }
+
+        if (z + 1 == ze || ((z + 1) & (SP_SLAB - 1)) == 0) {
+            float w = tmax;
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) w = fmaxf(w, __shfl_xor(w, off, 64));
+            if ((tid & 63) == 0) atomicMax(&a.meta.a_out[z >> 4], __float_as_uint(w * s_out));
+            tmax = 0.f;
+        }
+
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) q[j][i] = q[j][i + 1];
+            pp[j] = pp_n[j];
+            vv[j] = vv_n[j];
+        }
+    }
+}
+
 // One sweep over the block's tile and z-chunk.
 //   TX: tile width in points (4 per lane), TY: tile height in rows,
 //   RY: adjacent rows per thread (register blocking in y), T: storage type.
 template <int TX, int TY, int RY, int MODE, typename T>
 __device__ __forceinline__ void star25_body(const SweepArgs &a, const int lin) {
+    if constexpr (MODE == MODE_WAVE && std::is_same<T, _Float16>::value) {
+        star25_wave_h<TX, TY, RY>(a, lin);
+        return;
+    }
     typedef Io<T> IO;
     typedef typename IO::raw raw;
     constexpr int LX = TX / 4;           // lanes per tile row
@@ -610,6 +886,7 @@ hipError_t launch_batch_cfg(int mode, const TileCfg &t, const SweepArgs *args, c
     if (t.tx == 256 && t.ty == 16 && t.ry == 2) return launch_batch_t<256, 16, 2, T>(mode, args, table, nblk, s);
     if (t.tx == 128 && t.ty == 16 && t.ry == 2) return launch_batch_t<128, 16, 2, T>(mode, args, table, nblk, s);
     if (t.tx == 64 && t.ty == 16 && t.ry == 1) return launch_batch_t<64, 16, 1, T>(mode, args, table, nblk, s);
+    if (t.tx == 256 && t.ty == 16 && t.ry == 1) return launch_batch_t<256, 16, 1, T>(mode, args, table, nblk, s);
     return hipErrorInvalidValue;
 }
 
@@ -643,6 +920,8 @@ hipError_t launch_cfg(int mode, const TileCfg &t, const SweepArgs &a, hipStream_
     if (t.tx == 64 && t.ty == 16 && t.ry == 1) return launch_t<64, 16, 1, T>(mode, a, s);
     if (t.tx == 128 && t.ty == 32 && t.ry == 2) return launch_t<128, 32, 2, T>(mode, a, s);
     if (t.tx == 256 && t.ty == 8 && t.ry == 2) return launch_t<256, 8, 2, T>(mode, a, s);
+    if (t.tx == 256 && t.ty == 16 && t.ry == 1) return launch_t<256, 16, 1, T>(mode, a, s);
+    if (t.tx == 256 && t.ty == 8 && t.ry == 1) return launch_t<256, 8, 1, T>(mode, a, s);
     return hipErrorInvalidValue;
 }
 
@@ -651,18 +930,29 @@ hipError_t launch_cfg(int mode, const TileCfg &t, const SweepArgs &a, hipStream_
 bool tile_supported(const TileCfg &t) {
     return (t.tx == 256 && t.ty == 16 && t.ry == 2) || (t.tx == 128 && t.ty == 16 && t.ry == 2) ||
            (t.tx == 64 && t.ty == 16 && t.ry == 1) || (t.tx == 128 && t.ty == 32 && t.ry == 2) ||
-           (t.tx == 256 && t.ty == 8 && t.ry == 2);
+           (t.tx == 256 && t.ty == 8 && t.ry == 2) || (t.tx == 256 && t.ty == 16 && t.ry == 1) ||
+           (t.tx == 256 && t.ty == 8 && t.ry == 1);
 }
 
-TileCfg choose_tiles(int nx, int ny, int nz) {
+TileCfg choose_tiles(int nx, int ny, int nz, int dtype) {
     // Widest tile that does not waste more than a quarter of its columns on
     // the ragged x edge: wide tiles keep the x-halo (one 128-byte line per
     // side per row) and the y-halo rows small relative to the tile, and two
-    // rows per thread share their y-neighbour reads.  Then split z until
-    // there are enough blocks for 4 waves per SIMD (256 blocks of 512 threads
-    // or 512 of 256), down to 16-plane chunks (each chunk re-reads 8 planes
-    // of u, mostly from L2).
-    static const int cand[3][3] = {{256, 16, 2}, {128, 16, 2}, {64, 16, 1}};
+    // rows per thread share their y-neighbour reads.  The candidates depend
+    // on the storage type, because what limits each kernel differs:
+    //  * FP32 (184 VGPRs, 16-byte accesses): 512-thread 256x16x2 tiles;
+    //  * FP16 (about 150 VGPRs, 8-byte accesses, latency-bound): 256-thread
+    //    tiles, so that three blocks (three waves per SIMD) fit a CU and
+    //    keep more bytes in flight;
+    //  * BF16 (about 107 VGPRs with one row per thread): 1024-thread
+    //    256x16x1 tiles at four waves per SIMD.
+    // Then split z until there are enough blocks to fill the chip (256
+    // blocks of 512 or 1024 threads, 512 of 256), down to 16-plane chunks
+    // (each chunk re-reads 8 planes of u, mostly from L2).
+    static const int c32[3][3] = {{256, 16, 2}, {128, 16, 2}, {64, 16, 1}};
+    static const int c16[3][3] = {{128, 16, 2}, {128, 16, 2}, {64, 16, 1}};
+    static const int cbf[3][3] = {{256, 16, 1}, {128, 16, 2}, {64, 16, 1}};
+    const int (*cand)[3] = dtype == SP_F16 ? c16 : (dtype == SP_BF16 ? cbf : c32);
     TileCfg t;
     for (int c = 0; c < 3; ++c) {
         t.tx = cand[c][0];
@@ -673,13 +963,18 @@ TileCfg choose_tiles(int nx, int ny, int nz) {
     }
     const int tiles = ((nx + t.tx - 1) / t.tx) * ((ny + t.ty - 1) / t.ty);
     const int threads = (t.tx / 4) * (t.ty / t.ry);
-    const int want = 256 * (512 / threads);
+    const int want = threads >= 512 ? 256 : 256 * (512 / threads);
     const int chunks = (want + tiles - 1) / tiles;
     int zc = (nz + chunks - 1) / chunks;
     if (zc < 16) zc = 16;
     if (zc > nz) zc = nz;
     t.zchunk = zc < 1 ? 1 : zc;
     return t;
+}
+
+bool batch_supported(const TileCfg &t) {
+    return (t.tx == 256 && t.ty == 16 && (t.ry == 2 || t.ry == 1)) ||
+           (t.tx == 128 && t.ty == 16 && t.ry == 2) || (t.tx == 64 && t.ty == 16 && t.ry == 1);
 }
 
 hipError_t launch_sweep(int mode, int dtype, const TileCfg &t, const SweepArgs &a, hipStream_t s) {

@@ -40,9 +40,16 @@ def _state_from(fields, g, q_prev, s_prev, q_cur, s_cur, fmt):
     return ws
 
 
+LOWP_TILES = ["", "128x16x2", "256x8x2", "256x16x1", "256x8x1", "64x16x1x7", "256x16x2x20"]
+
+
+@pytest.mark.parametrize("tile", LOWP_TILES)
 @pytest.mark.parametrize("fmt", ["f16", "bf16"])
-def test_single_step_parity(gpu_lib, fmt):
+def test_single_step_parity(gpu_lib, fmt, tile, monkeypatch):
+    # every compiled launch configuration ("" = the default choice)
     from paper_2309_04671_amd import fields, lib
+    if tile:
+        monkeypatch.setenv("SP_TILE", tile)
     nx, ny, nz = 301, 45, 70                    # ragged in x, y and in the last slab
     g = lib.grid_init(nx, ny, nz, FMT[fmt])
     gv = lib.grid_init(nx, ny, nz)

@@ -240,8 +240,8 @@ def test_apply_full_size_sampled_parity(gpu_lib):
     assert e["rel_l2"] <= TOL_SWEEP
 
 
-TILE_CONFIGS = ["64x16x1", "128x16x2", "128x32x2", "256x16x2", "256x8x2",
-                "64x16x1x7", "128x16x2x33", "256x16x2x40"]
+TILE_CONFIGS = ["64x16x1", "128x16x2", "128x32x2", "256x16x2", "256x8x2", "256x16x1", "256x8x1",
+                "64x16x1x7", "128x16x2x33", "256x16x2x40", "256x8x1x9"]
 
 
 @pytest.mark.parametrize("tile", TILE_CONFIGS)
