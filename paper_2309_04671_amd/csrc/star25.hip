@@ -384,12 +384,15 @@ __device__ __forceinline__ void star25_wave_h(const SweepArgs &a, const int lin)
             }
             if (st_ok[j]) {
                 _Float16 *o = out + (int64_t)z * sz + own[j];
-                const raw enc = IO::enc(res, inv_out);
-                const f4v mg = IO::mag(enc);
-                float mm = mg.x;
-                if (x + 1 < a.nx) mm = fmaxf(mm, mg.y);
-                if (x + 2 < a.nx) mm = fmaxf(mm, mg.z);
-                if (x + 3 < a.nx) mm = fmaxf(mm, mg.w);
+                // the slab maximum is taken on the scaled FP32 values and
+                // rounded once per wave below: rounding to nearest even is
+                // monotone and odd, so max |round(v)| = round(max |v|)
+                const f4v sc = res * inv_out;
+                const raw enc = __builtin_convertvector(sc, raw);
+                float mm = fabsf(sc.x);
+                if (x + 1 < a.nx) mm = fmaxf(mm, fabsf(sc.y));
+                if (x + 2 < a.nx) mm = fmaxf(mm, fabsf(sc.z));
+                if (x + 3 < a.nx) mm = fmaxf(mm, fabsf(sc.w));
                 tmax = fmaxf(tmax, mm);
                 if (x + 4 <= a.nx) {
                     IO::st_nt(o, enc);
@@ -405,6 +408,7 @@ __device__ __forceinline__ void star25_wave_h(const SweepArgs &a, const int lin)
             float w = tmax;
 #pragma unroll
             for (int off = 32; off >= 1; off >>= 1) w = fmaxf(w, __shfl_xor(w, off, 64));
+            w = (float)(_Float16)w;                 // the stored magnitude
             if ((tid & 63) == 0) atomicMax(&a.meta.a_out[z >> 4], __float_as_uint(w * s_out));
             tmax = 0.f;
         }
@@ -940,30 +944,34 @@ TileCfg choose_tiles(int nx, int ny, int nz, int dtype) {
     // side per row) and the y-halo rows small relative to the tile, and two
     // rows per thread share their y-neighbour reads.  The candidates depend
     // on the storage type, because what limits each kernel differs:
-    //  * FP32 (184 VGPRs, 16-byte accesses): 512-thread 256x16x2 tiles;
+    //  * FP32 (184 VGPRs, 16-byte accesses): 512-thread 256x16x2 tiles, one
+    //    block per CU, z split only when there are fewer than 256 tiles;
     //  * FP16 (about 150 VGPRs, 8-byte accesses, latency-bound): 256-thread
-    //    tiles, so that three blocks (three waves per SIMD) fit a CU and
-    //    keep more bytes in flight;
+    //    tiles, three resident per CU, and many short z-chunks (about 4096
+    //    blocks) so that the CUs stay evenly loaded;
     //  * BF16 (about 107 VGPRs with one row per thread): 1024-thread
-    //    256x16x1 tiles at four waves per SIMD.
-    // Then split z until there are enough blocks to fill the chip (256
-    // blocks of 512 or 1024 threads, 512 of 256), down to 16-plane chunks
-    // (each chunk re-reads 8 planes of u, mostly from L2).
-    static const int c32[3][3] = {{256, 16, 2}, {128, 16, 2}, {64, 16, 1}};
-    static const int c16[3][3] = {{128, 16, 2}, {128, 16, 2}, {64, 16, 1}};
-    static const int cbf[3][3] = {{256, 16, 1}, {128, 16, 2}, {64, 16, 1}};
-    const int (*cand)[3] = dtype == SP_F16 ? c16 : (dtype == SP_BF16 ? cbf : c32);
+    //    256x16x1 tiles at four waves per SIMD (about 512 blocks) where the
+    //    grid has at least two of them across x, else the FP16 choice.
+    // z-chunks are at least 16 planes (each chunk re-reads 8 planes of u,
+    // mostly from L2).  These targets are measured optima on MI355X.
+    struct Cand {
+        int tx, ty, ry, want, min_tiles_x;
+    };
+    static const Cand c32[3] = {{256, 16, 2, 256, 1}, {128, 16, 2, 512, 1}, {64, 16, 1, 512, 1}};
+    static const Cand c16[3] = {{128, 16, 2, 4096, 1}, {128, 16, 2, 4096, 1}, {64, 16, 1, 4096, 1}};
+    static const Cand cbf[3] = {{256, 16, 1, 512, 2}, {128, 16, 2, 4096, 1}, {64, 16, 1, 4096, 1}};
+    const Cand *cand = dtype == SP_F16 ? c16 : (dtype == SP_BF16 ? cbf : c32);
     TileCfg t;
+    int want = 256;
     for (int c = 0; c < 3; ++c) {
-        t.tx = cand[c][0];
-        t.ty = cand[c][1];
-        t.ry = cand[c][2];
+        t.tx = cand[c].tx;
+        t.ty = cand[c].ty;
+        t.ry = cand[c].ry;
+        want = cand[c].want;
         const int tiles_x = (nx + t.tx - 1) / t.tx;
-        if (4 * tiles_x * t.tx <= 5 * nx || c == 2) break;
+        if ((4 * tiles_x * t.tx <= 5 * nx && tiles_x >= cand[c].min_tiles_x) || c == 2) break;
     }
     const int tiles = ((nx + t.tx - 1) / t.tx) * ((ny + t.ty - 1) / t.ty);
-    const int threads = (t.tx / 4) * (t.ty / t.ry);
-    const int want = threads >= 512 ? 256 : 256 * (512 / threads);
     const int chunks = (want + tiles - 1) / tiles;
     int zc = (nz + chunks - 1) / chunks;
     if (zc < 16) zc = 16;
