@@ -145,7 +145,7 @@ def leg_suite(torch, lib, fields, synth, sweeps=10):
     def timed(g, fn):
         a, b = fields.Field(g), fields.Field(g)
         a.set_interior(torch.rand((g.nz, g.ny, g.nx), generator=torch.Generator().manual_seed(0)))
-        fn(g, a, b, 1)                                   # warm-up sweep
+        fn(g, a, b, 3)                                   # warm-up sweeps (fresh buffers)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         fn(g, a, b, sweeps)
@@ -164,6 +164,19 @@ def leg_suite(torch, lib, fields, synth, sweeps=10):
                      "bound": bound, "frac": round(frac, 4), "finite": ok}
 
     co = lib.coeffs(synth.star25_coeffs())
+    # C0: one 64^3 sweep is launch-latency bound (1.5 MB fits in L2); time
+    # per sweep over 1000 back-to-back sweeps
+    g = lib.grid_init(64, 64, 64)
+    a, b = fields.Field(g), fields.Field(g)
+    a.set_interior(torch.rand((64, 64, 64), generator=torch.Generator().manual_seed(0)))
+    lib.sp_stencil_apply(g, co, 10, a.ptr, b.ptr, stream=stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    lib.sp_stencil_apply(g, co, 1000, a.ptr, b.ptr, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    out["apply25_64^3_latency"] = {"us_per_sweep": round(e0.elapsed_time(e1), 2),
+                                   "note": "1000 back-to-back sweeps, launch-latency bound"}
     for n3 in ((512, 512, 512), (1024, 1024, 512)):
         g = lib.grid_init(*n3)
         ms, ok = timed(g, lambda g, a, b, k: lib.sp_stencil_apply(g, co, k, a.ptr, b.ptr, stream=stream))
@@ -176,7 +189,7 @@ def leg_suite(torch, lib, fields, synth, sweeps=10):
         flops = SUITE_FLOPS.get(name, 2 * int(np.count_nonzero(w)) - 1)
         record(name, g, ms, flops, ok)
         torch.cuda.empty_cache()
-    out["config"] = ("%d sweeps each after one warm-up sweep; inputs U[0,1) FP32; seeded positive "
+    out["config"] = ("%d sweeps each after three warm-up sweeps; inputs U[0,1) FP32; seeded positive "
                      "weights (sum 1)" % sweeps)
     return out
 

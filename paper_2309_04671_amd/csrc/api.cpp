@@ -83,8 +83,8 @@ void fill_tiling(sp::SweepArgs &a, const sp::TileCfg &t) {
 // Launch configuration for a grid; SP_TILE=TXxTYxRY[xZC] overrides it for
 // tuning.  Returns false (with the error set) for a configuration that is
 // not compiled in.
-bool tiles_for(const sp_grid *g, sp::TileCfg *out, const char *who) {
-    sp::TileCfg t = sp::choose_tiles(g->nx, g->ny, g->nz, g->dtype);
+bool tiles_for(const sp_grid *g, sp::TileCfg *out, const char *who, int mode = sp::MODE_WAVE) {
+    sp::TileCfg t = sp::choose_tiles(g->nx, g->ny, g->nz, g->dtype, mode);
     // Optional override for tuning: SP_TILE=TXxTYxRY[xZC]
     if (const char *e = std::getenv("SP_TILE")) {
         int tx = 0, ty = 0, ry = 0, zc = 0;
@@ -224,7 +224,7 @@ int sp_stencil_apply(const sp_grid *g, const sp_coeffs *c, int sweeps, void *u, 
     a.sz = g->pitch_x * g->pitch_y;
     a.c = to_f32(c);
     sp::TileCfg t;
-    if (!tiles_for(g, &t, "sp_stencil_apply")) return SP_EINVAL;
+    if (!tiles_for(g, &t, "sp_stencil_apply", sp::MODE_APPLY)) return SP_EINVAL;
     fill_tiling(a, t);
     float *bufs[2] = {static_cast<float *>(u) + g->origin, static_cast<float *>(v) + g->origin};
     hipStream_t s = static_cast<hipStream_t>(stream);

@@ -77,7 +77,8 @@ struct TileCfg {
     int zchunk;          // planes per block
 };
 
-TileCfg choose_tiles(int nx, int ny, int nz, int dtype);
+// Launch configuration of the k_star25 sweeps for a grid, storage type and mode.
+TileCfg choose_tiles(int nx, int ny, int nz, int dtype, int mode);
 // Configurations the batched (multi-grid) sweep is compiled for.
 bool batch_supported(const TileCfg &t);
 bool tile_supported(const TileCfg &t);

@@ -938,7 +938,7 @@ bool tile_supported(const TileCfg &t) {
            (t.tx == 256 && t.ty == 8 && t.ry == 1);
 }
 
-TileCfg choose_tiles(int nx, int ny, int nz, int dtype) {
+TileCfg choose_tiles(int nx, int ny, int nz, int dtype, int mode) {
     // Widest tile that does not waste more than a quarter of its columns on
     // the ragged x edge: wide tiles keep the x-halo (one 128-byte line per
     // side per row) and the y-halo rows small relative to the tile, and two
@@ -951,7 +951,9 @@ TileCfg choose_tiles(int nx, int ny, int nz, int dtype) {
     //    blocks) so that the CUs stay evenly loaded;
     //  * BF16 (about 107 VGPRs with one row per thread): 1024-thread
     //    256x16x1 tiles at four waves per SIMD (about 512 blocks) where the
-    //    grid has at least two of them across x, else the FP16 choice.
+    //    grid has at least two of them across x, else the FP16 choice;
+    //  * the FP32 APPLY sweep (8 B per point) runs best on 256x16x1 tiles
+    //    too, but with one long z-chunk per tile (about 256 blocks).
     // z-chunks are at least 16 planes (each chunk re-reads 8 planes of u,
     // mostly from L2).  These targets are measured optima on MI355X.
     struct Cand {
@@ -960,7 +962,11 @@ TileCfg choose_tiles(int nx, int ny, int nz, int dtype) {
     static const Cand c32[3] = {{256, 16, 2, 256, 1}, {128, 16, 2, 512, 1}, {64, 16, 1, 512, 1}};
     static const Cand c16[3] = {{128, 16, 2, 4096, 1}, {128, 16, 2, 4096, 1}, {64, 16, 1, 4096, 1}};
     static const Cand cbf[3] = {{256, 16, 1, 512, 2}, {128, 16, 2, 4096, 1}, {64, 16, 1, 4096, 1}};
-    const Cand *cand = dtype == SP_F16 ? c16 : (dtype == SP_BF16 ? cbf : c32);
+    static const Cand cap[3] = {{256, 16, 1, 256, 2}, {128, 16, 2, 512, 1}, {64, 16, 1, 512, 1}};
+    const Cand *cand = dtype == SP_F16    ? c16
+                       : dtype == SP_BF16 ? cbf
+                       : mode == MODE_APPLY ? cap
+                                            : c32;
     TileCfg t;
     int want = 256;
     for (int c = 0; c < 3; ++c) {
