@@ -327,10 +327,10 @@ template <int R, bool BOX>
 hipError_t run2(const float *w, const SuiteArgs &a, hipStream_t s) {
     Tile2 t;
     t.tiles_x = (a.nx + 255) / 256;
-    // rows per wave: enough waves to fill the chip, at least 8r rows so the
-    // 2r re-read rows stay a small share
+    // rows per wave: about 4096 waves (16 per CU; measured best), at least
+    // 8r rows so the 2r re-read rows stay a small share
     const int64_t strips = (int64_t)t.tiles_x * a.nz;
-    int64_t yc = (strips * a.ny + 8191) / 8192;
+    int64_t yc = (strips * a.ny + 4095) / 4096;
     yc = std::max<int64_t>(yc, 8 * R);
     t.ychunk = (int)std::min<int64_t>(yc, a.ny);
     const int nchunks = (a.ny + t.ychunk - 1) / t.ychunk;
@@ -352,8 +352,9 @@ hipError_t run3(const float *w, const SuiteArgs &a, hipStream_t s) {
     t.tiles_x = (a.nx + 255) / 256;
     t.tiles_y = (a.ny + TY - 1) / TY;
     const int64_t tiles = (int64_t)t.tiles_x * t.tiles_y;
-    // split z only as far as needed for ~2 blocks per CU
-    const int64_t want = 512;
+    // split z only as far as needed for about one block per CU: longer
+    // chunks re-read fewer frame planes (measured best)
+    const int64_t want = 256;
     int64_t chunks = (want + tiles - 1) / tiles;
     int64_t zc = (a.nz + chunks - 1) / chunks;
     zc = std::max<int64_t>(zc, std::min<int64_t>(4 * R, a.nz));
