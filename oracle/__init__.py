@@ -52,6 +52,9 @@ def _load():
     lib.ref_adjoint_grad.restype = d
     lib.ref_stencil_general.argtypes = [i, i, i, i, i, _dp, _dp, _dp]
     lib.ref_stencil_general.restype = None
+    lib.ref_wave_pml_run.argtypes = [i, i, i, _dp, d, d, _dp, _dp, d, i, i, _ip, _dp, i, _ip, _dp,
+                                     _dp, _dp, _dp]
+    lib.ref_wave_pml_run.restype = None
     lib.ref_num_threads.argtypes = []
     lib.ref_num_threads.restype = i
     _lib = lib
@@ -191,3 +194,27 @@ def stencil_general(u, w, ndim: int, sweeps: int = 1, frame=None) -> np.ndarray:
         cur = nxt
     out = cur[hz:hz + nz, HALO:-HALO, HALO:-HALO].copy()
     return out[0] if flat2d else out
+
+
+def wave_pml_run(coeffs, v, eta_pad, dt, dx, nsteps, src=None, amp=None, rec=None, prev=None,
+                 cur=None, psi=None, alpha=0.0):
+    """Leapfrog with the absorbing layer (ref.c ``ref_wave_pml_run``).
+    eta_pad: padded (nz+8, ny+8, nx+8) damping field in 1/s, frame read.
+    Returns dict(prev, cur, psi (padded), traces)."""
+    lib = _load()
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    nz, ny, nx = v.shape
+    eta = np.ascontiguousarray(eta_pad, dtype=np.float64)
+    assert eta.shape == (nz + 8, ny + 8, nx + 8)
+    prev = np.zeros((nz + 8, ny + 8, nx + 8)) if prev is None else np.array(prev, dtype=np.float64)
+    cur = np.zeros_like(prev) if cur is None else np.array(cur, dtype=np.float64)
+    psi = np.zeros_like(prev) if psi is None else np.array(psi, dtype=np.float64)
+    src = np.zeros((0, 3), np.int32) if src is None else np.ascontiguousarray(src, dtype=np.int32)
+    nsrc = len(src)
+    amp = np.zeros((nsteps, max(nsrc, 1))) if amp is None else np.ascontiguousarray(amp, dtype=np.float64)
+    rec = np.zeros((0, 3), np.int32) if rec is None else np.ascontiguousarray(rec, dtype=np.int32)
+    traces = np.zeros((nsteps, max(len(rec), 1)))
+    lib.ref_wave_pml_run(nx, ny, nz, _p(coeff_vector(coeffs)), float(dt), float(dx), _p(v), _p(eta),
+                         float(alpha), int(nsteps), nsrc, _p(src, _ip), _p(amp), len(rec), _p(rec, _ip),
+                         _p(traces), _p(prev), _p(cur), _p(psi))
+    return {"prev": prev, "cur": cur, "psi": psi, "traces": traces[:, :len(rec)]}

@@ -312,3 +312,79 @@ void ref_stencil_general(int nx, int ny, int nz, int ndim, int r, const double *
                 out[((int64_t)(z + hz) * py + (y + H)) * px + (x + H)] = s;
             }
 }
+
+/*
+ * Leapfrog with an absorbing perfectly-matched-type layer (the inner + PML
+ * regions of the paper's Sec. 2.2; the paper names the PML but does not
+ * give its equations).  The reading taken: complex stretching of all three
+ * coordinates by the same position-dependent factor 1 + eta/(i w), which
+ * turns the wave equation into
+ *     (d/dt + eta)^2 u = V^2 (lap u + phi),
+ *     (d/dt + eta + alpha) phi = -grad eta . grad u,
+ * (with alpha = 0 exactly the PML in 1D).  The frequency shift alpha > 0 in
+ * the auxiliary equation, as in frequency-shifted (convolutional) PMLs,
+ * removes a slowly growing zero-frequency mode that the unshifted isotropic
+ * form develops in long runs.  Centred differences in time, with psi =
+ * dx^2 phi held at half steps, eta in 1/s, a = eta dt, b = a + alpha dt:
+ *     psi^{n+1/2} = [ (1 - b/2) psi^{n-1/2} - dt G^n ] / (1 + b/2)
+ *     u^{n+1} = [ (2 - a^2) u^n - (1 - a) u^{n-1}
+ *                 + m (L u^n + (psi^{n-1/2} + psi^{n+1/2}) / 2) ] / (1 + a)
+ *     G^n = 1/4 sum over axes (eta(+1) - eta(-1)) (u^n(+1) - u^n(-1))
+ * (the 7-point star of grad eta . grad u in index units); then the sources
+ * of Algorithm 1 and the receivers as in ref_wave_run.  Where eta and its
+ * neighbours are 0 (and psi is 0) this is the plain leapfrog.
+ * eta: padded like the fields (its frame is read); psi: padded, interior
+ * used, updated in place.  prev/cur as in ref_wave_run.
+ */
+void ref_wave_pml_run(int nx, int ny, int nz, const double *c, double dt, double dx,
+                      const double *v, const double *eta, double alpha, int nsteps,
+                      int nsrc, const int32_t *src, const double *amp,
+                      int nrec, const int32_t *rec, double *traces,
+                      double *prev, double *cur, double *psi)
+{
+    const int64_t np = padded_count(nx, ny, nz);
+    double *lap = (double *)calloc((size_t)np, sizeof(double));
+    double *bufs[2] = {prev, cur};
+    int ip = 0, ic = 1;
+    const double r = dt / dx;
+    const int64_t sx = 1, sy = nx + 2 * H, sz = (int64_t)(nx + 2 * H) * (ny + 2 * H);
+    for (int n = 0; n < nsteps; ++n) {
+        double *up = bufs[ip], *uc = bufs[ic];
+        ref_laplacian(nx, ny, nz, c, uc, lap);
+#pragma omp parallel for schedule(static)
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) {
+                    const int64_t i = at(nx, ny, x, y, z);
+                    const double vv = v[((int64_t)z * ny + y) * nx + x];
+                    const double m = (vv * r) * (vv * r);
+                    const double a = eta[i] * dt;
+                    const double G = 0.25 * ((eta[i + sx] - eta[i - sx]) * (uc[i + sx] - uc[i - sx]) +
+                                             (eta[i + sy] - eta[i - sy]) * (uc[i + sy] - uc[i - sy]) +
+                                             (eta[i + sz] - eta[i - sz]) * (uc[i + sz] - uc[i - sz]));
+                    const double b = a + alpha * dt;
+                    const double pnew = ((1.0 - 0.5 * b) * psi[i] - dt * G) / (1.0 + 0.5 * b);
+                    up[i] = ((2.0 - a * a) * uc[i] - (1.0 - a) * up[i] +
+                             m * (lap[i] + 0.5 * (psi[i] + pnew))) / (1.0 + a);
+                    psi[i] = pnew;
+                }
+        for (int s = 0; s < nsrc; ++s) {
+            int x = src[3 * s], y = src[3 * s + 1], z = src[3 * s + 2];
+            double vv = v[((int64_t)z * ny + y) * nx + x];
+            up[at(nx, ny, x, y, z)] += dt * dt * vv * vv * amp[(int64_t)n * nsrc + s];
+        }
+        for (int q = 0; q < nrec; ++q) {
+            int x = rec[3 * q], y = rec[3 * q + 1], z = rec[3 * q + 2];
+            traces[(int64_t)n * nrec + q] = up[at(nx, ny, x, y, z)];
+        }
+        int t = ip; ip = ic; ic = t;
+    }
+    if (bufs[ic] != cur) {
+        double *tmp = (double *)malloc((size_t)np * sizeof(double));
+        memcpy(tmp, cur, (size_t)np * sizeof(double));
+        memcpy(cur, prev, (size_t)np * sizeof(double));
+        memcpy(prev, tmp, (size_t)np * sizeof(double));
+        free(tmp);
+    }
+    free(lap);
+}

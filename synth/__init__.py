@@ -232,3 +232,26 @@ def suite_field(shape, seed: int, lo: float = 1e-4, hi: float = 1e5) -> np.ndarr
     rng = np.random.default_rng(seed)
     a = np.exp(rng.uniform(np.log(lo), np.log(hi), shape))
     return a.astype(np.float32).astype(np.float64)
+
+
+# ---------------------------------------------------------------------------
+# Absorbing layer (the paper's PML region).  Damping profile of a layer of
+# `width` cells on every face: eta = eta_max * sum over axes (d_a / width)^2,
+# d_a = max(0, width - 1 - a, a - (n_a - width)) the depth of index a into
+# the layer (0 on the layer's inner face, growing into the halo frame).  The
+# cells next to the inner box have eta = 0 on both sides, so grad eta
+# vanishes on the inner box.
+
+def pml_eta_max(v_max: float, width: int, dx: float, reflection: float = 1e-3) -> float:
+    """Peak damping (1/s) of a quadratic profile with the given nominal
+    reflection coefficient: 3 v ln(1/R) / (2 W dx) (Collino and Tsogka)."""
+    return 3.0 * v_max * math.log(1.0 / reflection) / (2.0 * width * dx)
+
+
+def pml_profile(nx: int, ny: int, nz: int, width: int, eta_max: float) -> np.ndarray:
+    """Damping on the padded (nz+8, ny+8, nx+8) array (frame included), FP64."""
+    def depth(n):
+        a = np.arange(-HALO, n + HALO)
+        return np.maximum(0, np.maximum(width - 1 - a, a - (n - width))) / width
+    dz, dy, dx_ = depth(nz), depth(ny), depth(nx)
+    return eta_max * (dz[:, None, None] ** 2 + dy[None, :, None] ** 2 + dx_[None, None, :] ** 2)
