@@ -284,6 +284,62 @@ def leg_adjoint(torch, lib, fields, synth, n=256, nt=1000, ckpt=32):
 
 
 
+def leg_pml(torch, lib, fields, synth, nt=100, width=32):
+    """Leapfrog with the absorbing layer on the 1024x1024x512 workload (layer
+    of `width` cells on every face): the seven-region map (inner box by the
+    streaming kernel, six slabs by the layer kernel), the unified map (layer
+    kernel everywhere) and the plain leapfrog, nt steps each after a
+    warm-up run; the layer kernel's own rate at its 28 B per point."""
+    import numpy as np
+    nx, ny, nz = NX, NY, NZ
+    g = lib.grid_init(nx, ny, nz)
+    v = synth.layered_velocity(nx, ny, nz, 0)
+    V = fields.Field(g).set_interior(v)
+    dx = 10.0
+    dt = synth.cfl_dt(v, dx)
+    E = fields.Field(g)
+    lib.sp_pml_profile(g, width, synth.pml_eta_max(float(v.max()), width, dx), E.ptr)
+    del v
+    PSI = fields.Field(g)
+    amp = torch.tensor(synth.ricker(nt, dt)[:, None], dtype=torch.float32, device="cuda")
+    src = lib.make_sources([[nx // 2, ny // 2, nz // 2]], amp.data_ptr(), 1)
+    co = lib.coeffs(synth.star25_coeffs())
+    ws = fields.WaveState(g)
+    stream = torch.cuda.current_stream()
+    alpha = np.pi * 15.0
+    runs = {"plain": lambda: lib.sp_wave_step(g, co, dt, dx, g, V.ptr, ws.st, nt, src=src, stream=stream),
+            "seven_region": lambda: lib.sp_wave_step_pml(g, co, dt, dx, g, V.ptr, ws.st, nt,
+                                                         lib.make_pml(width, E.ptr, PSI.ptr, alpha, 1),
+                                                         src=src, stream=stream),
+            "unified": lambda: lib.sp_wave_step_pml(g, co, dt, dx, g, V.ptr, ws.st, nt,
+                                                    lib.make_pml(width, E.ptr, PSI.ptr, alpha, 0),
+                                                    src=src, stream=stream)}
+    out = {}
+    for name, fn in runs.items():
+        ws.reset()
+        fn()
+        ms = []
+        for _ in range(3):
+            ws.reset()
+            PSI.buf.zero_()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1) / nt)
+        m = sorted(ms)[1]
+        out[name] = {"us_per_step": round(m * 1e3, 1), "gpts": round(nx * ny * nz / m / 1e6, 1)}
+    inner = (nx - 2 * width) * (ny - 2 * width) * (nz - 2 * width)
+    layer_pts = nx * ny * nz - inner
+    layer_us = out["seven_region"]["us_per_step"] - out["plain"]["us_per_step"] * inner / (nx * ny * nz)
+    out["layer_kernel"] = {"points": layer_pts, "us_per_step_est": round(layer_us, 1),
+                           "gbs_at_28B": round(28 * layer_pts / (layer_us * 1e3), 1),
+                           "note": "layer time = seven-region step minus the inner box at the plain rate"}
+    out["config"] = "1024x1024x512, layer %d cells, alpha pi*15 1/s, %d steps, median of 3" % (width, nt)
+    return out
+
+
 SERVE_SHAPES = [(128, 128, 128), (192, 192, 160), (256, 256, 256), (384, 384, 256)]
 
 
@@ -395,7 +451,7 @@ def main():
                     help="override the headline grid (profiling runs only)")
     ap.add_argument("--no-headline", action="store_true",
                     help="skip the headline run (profiling runs of the extra legs)")
-    ap.add_argument("--legs", default="storage,storage_error,adjoint,suite,serve",
+    ap.add_argument("--legs", default="storage,storage_error,adjoint,pml,suite,serve",
                     help="extra measurements after the headline run (comma list; '' for none)")
     ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
                     help="instead of the benchmark, copy a GIB-sized buffer 4 times with torch "
@@ -518,6 +574,10 @@ def main():
     if "adjoint" in legs:
         log("adjoint gradient at 256^3")
         forms["adjoint_256"] = leg_adjoint(torch, lib, fields, synth)
+    if "pml" in legs:
+        log("absorbing layer")
+        forms["pml"] = leg_pml(torch, lib, fields, synth)
+        torch.cuda.empty_cache()
     if "suite" in legs:
         log("stencil suite")
         forms["suite"] = leg_suite(torch, lib, fields, synth)

@@ -269,6 +269,52 @@ int sp_energy(const sp_grid *g, const sp_coeffs *c, double dt, double dx,
               double *out, void *ws, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Absorbing layer: the inner and PML regions of Sec. 2.2.
+ *
+ * The paper surrounds the domain with a PML whose kernel applies the
+ * 25-point star plus a 7-point star to a second array, but gives no
+ * equations.  The layer here stretches all coordinates by one
+ * position-dependent factor, with a frequency shift alpha in the auxiliary
+ * equation (stable in long runs):
+ *     (d/dt + eta)^2 u = V^2 (lap u + phi),
+ *     (d/dt + eta + alpha) phi = -grad eta . grad u,
+ * discretised centred in time with psi = dx^2 phi at half steps
+ * (a = eta dt, b = a + alpha dt, m = (v dt / dx)^2):
+ *     psi^{n+1/2} = [(1 - b/2) psi^{n-1/2} - dt G] / (1 + b/2),
+ *     G = 1/4 sum over axes (eta(+1) - eta(-1)) (u^n(+1) - u^n(-1)),
+ *     u^{n+1} = [(2 - a^2) u^n - (1 - a) u^{n-1}
+ *                + m (L u^n + (psi^{n-1/2} + psi^{n+1/2}) / 2)] / (1 + a),
+ * then the sources and receivers of sp_wave_step.  Where eta and its
+ * neighbours are zero this is the plain leapfrog.
+ * ---------------------------------------------------------------------- */
+
+#define SP_PML_UNIFIED 0   /* the layer kernel over the whole interior */
+#define SP_PML_SEVEN   1   /* inner box by the leapfrog kernel, 6 slabs by the layer kernel */
+
+typedef struct {
+    int32_t width;          /* W: layer cells on every face (SEVEN: W % 4 == 0, 4 <= W, 2W < n) */
+    int32_t decomposition;  /* SP_PML_UNIFIED or SP_PML_SEVEN (the paper's region maps) */
+    double alpha;           /* frequency shift of the auxiliary equation (1/s), >= 0 */
+    const float *eta;       /* DEVICE FP32 field on gv's layout, frame included: damping (1/s).
+                               SEVEN requires eta = 0 on the inner box [W, n-W) and on the
+                               cells next to it, as sp_pml_profile makes it */
+    float *psi;             /* DEVICE FP32 field on g's layout: psi, zero before the first step */
+} sp_pml;
+
+/* Fill eta (an FP32 field on gv, frame included) with the layer profile
+ *     eta = eta_max * sum over axes (d_a / W)^2,
+ *     d_a = max(0, W - 1 - a, a - (n_a - W)),
+ * zero on the inner box and on its neighbouring cells. */
+int sp_pml_profile(const sp_grid *gv, int width, double eta_max, float *eta, void *stream);
+
+/* nsteps leapfrog steps with the absorbing layer (FP32 grids only).  Same
+ * state, sources and receivers as sp_wave_step; g and gv must have the
+ * same layout. */
+int sp_wave_step_pml(const sp_grid *g, const sp_coeffs *c, double dt, double dx, const sp_grid *gv,
+                     const float *v, sp_wave_state *st, int nsteps, const sp_pml *pml,
+                     const sp_sources *src, const sp_receivers *rec, void *stream);
+
+/* ------------------------------------------------------------------------
  * Continuous-batching shot queue.
  *
  * Forward-modelling requests ("shots": one grid, velocity model, sources,

@@ -377,6 +377,131 @@ int sp_wave_step(const sp_grid *g, const sp_coeffs *c, double dt, double dx, con
     return ok();
 }
 
+int sp_pml_profile(const sp_grid *gv, int width, double eta_max, float *eta, void *stream) {
+    if (int e = check_grid(gv, "sp_pml_profile")) return e;
+    if (gv->dtype != SP_F32) return fail(SP_EINVAL, "sp_pml_profile: eta must be an FP32 grid");
+    if (!eta || !aligned16(eta)) return fail(SP_EINVAL, "sp_pml_profile: eta NULL or misaligned");
+    if (width < 1) return fail(SP_EINVAL, "sp_pml_profile: width must be >= 1");
+    if (!(eta_max >= 0) || !std::isfinite(eta_max))
+        return fail(SP_EINVAL, "sp_pml_profile: eta_max must be finite and >= 0");
+    hipError_t err = sp::launch_pml_profile(eta + gv->origin, gv->pitch_x, gv->pitch_x * gv->pitch_y,
+                                            gv->nx, gv->ny, gv->nz, width, (float)eta_max,
+                                            static_cast<hipStream_t>(stream));
+    if (err != hipSuccess) return fail(SP_EDEVICE, "sp_pml_profile: launch failed: %s", hipGetErrorString(err));
+    return ok();
+}
+
+int sp_wave_step_pml(const sp_grid *g, const sp_coeffs *c, double dt, double dx, const sp_grid *gv,
+                     const float *v, sp_wave_state *st, int nsteps, const sp_pml *pml,
+                     const sp_sources *src, const sp_receivers *rec, void *stream) {
+    const char *who = "sp_wave_step_pml";
+    sp::SweepArgs a;
+    sp::TileCfg t;
+    if (int e = prep_wave(who, g, c, dt, dx, gv, v, src, rec, &a, &t)) return e;
+    if (g->dtype != SP_F32) return fail(SP_EUNSUPPORTED, "%s: FP32 grids only", who);
+    if (g->pitch_x != gv->pitch_x || g->pitch_y != gv->pitch_y || g->origin != gv->origin)
+        return fail(SP_EINVAL, "%s: g and gv must have the same layout", who);
+    if (!st || !st->cur || !st->prev || st->meta) return fail(SP_EINVAL, "%s: bad state", who);
+    if (!pml || !pml->eta || !pml->psi) return fail(SP_EINVAL, "%s: NULL layer argument", who);
+    if (nsteps < 0 || st->step < 0) return fail(SP_EINVAL, "%s: negative step count", who);
+    if (!aligned16(st->cur) || !aligned16(st->prev) || !aligned16(pml->eta) || !aligned16(pml->psi))
+        return fail(SP_EINVAL, "%s: pointers must be 16-byte aligned", who);
+    if (overlaps(st->cur, st->prev, g->bytes)) return fail(SP_EINVAL, "%s: cur and prev overlap", who);
+    for (const void *f : {static_cast<const void *>(v), static_cast<const void *>(pml->eta),
+                          static_cast<const void *>(pml->psi)})
+        if (overlaps(st->cur, f, g->bytes) || overlaps(st->prev, f, g->bytes))
+            return fail(SP_EINVAL, "%s: a wavefield overlaps v, eta or psi", who);
+    if (overlaps(pml->psi, v, g->bytes) || overlaps(pml->psi, pml->eta, g->bytes))
+        return fail(SP_EINVAL, "%s: psi overlaps v or eta", who);
+    if (!(pml->alpha >= 0) || !std::isfinite(pml->alpha))
+        return fail(SP_EINVAL, "%s: alpha must be finite and >= 0", who);
+    const int W = pml->width, nx = g->nx, ny = g->ny, nz = g->nz;
+    const bool seven = pml->decomposition == SP_PML_SEVEN;
+    if (!seven && pml->decomposition != SP_PML_UNIFIED)
+        return fail(SP_EINVAL, "%s: unknown decomposition %d", who, pml->decomposition);
+    if (seven && (W < 4 || W % 4 != 0 || 2 * W >= nx || 2 * W >= ny || 2 * W >= nz))
+        return fail(SP_EINVAL, "%s: the seven-region map needs W %% 4 == 0, W >= 4 and 2W < n (W = %d)",
+                    who, W);
+    if (g->pitch_x * g->pitch_y >= ((int64_t)1 << 31))
+        return fail(SP_EUNSUPPORTED, "%s: planes of 2^31 or more elements", who);
+
+    // layer kernel arguments (whole-grid coordinates)
+    sp::PmlArgs pa;
+    std::memset(&pa, 0, sizeof pa);
+    pa.v = v + gv->origin;
+    pa.eta = pml->eta + gv->origin;
+    pa.psi = pml->psi + g->origin;
+    pa.nx = nx;
+    pa.ny = ny;
+    pa.nz = nz;
+    pa.sy = a.sy;
+    pa.sz = a.sz;
+    pa.m_scale = a.m_scale;
+    pa.dt = (float)dt;
+    pa.alpha_dt = (float)(pml->alpha * dt);
+    pa.c = a.c;
+    pa.src = a.src;
+    if (!seven) {
+        pa.nbox = 1;
+        pa.box[0] = {0, nx, 0, ny, 0, nz};
+    } else {
+        pa.nbox = 6;
+        pa.box[0] = {0, nx, 0, ny, 0, W};
+        pa.box[1] = {0, nx, 0, ny, nz - W, nz};
+        pa.box[2] = {0, nx, 0, W, W, nz - W};
+        pa.box[3] = {0, nx, ny - W, ny, W, nz - W};
+        pa.box[4] = {0, W, W, ny - W, W, nz - W};
+        pa.box[5] = {nx - W, nx, W, ny - W, W, nz - W};
+    }
+    // inner box: the streaming leapfrog kernel on the sub-grid [W, n - W)^3
+    sp::SweepArgs ai = a;
+    sp::TileCfg ti{};
+    const int64_t shift = (int64_t)W * (a.sz + a.sy + 1);
+    if (seven) {
+        ai.nx = nx - 2 * W;
+        ai.ny = ny - 2 * W;
+        ai.nz = nz - 2 * W;
+        ai.v = a.v + shift;
+        for (int q = 0; q < ai.src.n; ++q) {   // sources outside the box never match a point
+            ai.src.x[q] -= W;
+            ai.src.y[q] -= W;
+            ai.src.z[q] -= W;
+        }
+        ti = sp::choose_tiles(ai.nx, ai.ny, ai.nz, SP_F32, sp::MODE_WAVE);
+        fill_tiling(ai, ti);
+    }
+    const int nrec = rec ? rec->n : 0;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t step0 = st->step;
+    for (int k = 0; k < nsteps; ++k) {
+        const int64_t n = st->step;
+        float *cur = static_cast<float *>(st->cur) + g->origin;
+        float *prev = static_cast<float *>(st->prev) + g->origin;
+        const float *amp = a.src.n ? src->amp + n * src->amp_stride : nullptr;
+        hipError_t err = hipSuccess;
+        if (seven) {
+            ai.u = cur + shift;
+            ai.prev = prev + shift;
+            ai.out = prev + shift;
+            ai.src.amp = amp;
+            err = sp::launch_sweep(sp::MODE_WAVE, SP_F32, ti, ai, s);
+        }
+        pa.u = cur;
+        pa.prev = prev;
+        pa.src.amp = amp;
+        if (err == hipSuccess) err = sp::launch_pml(pa, s);
+        if (err == hipSuccess && nrec > 0)
+            err = sp::launch_record(SP_F32, prev, nullptr, a.sy, a.sz, nx, ny, nz, rec->xyz, nrec,
+                                    rec->traces + (n - step0) * rec->trace_stride, s);
+        if (err != hipSuccess)
+            return fail(SP_EDEVICE, "%s: launch failed at step %lld: %s", who, (long long)n,
+                        hipGetErrorString(err));
+        std::swap(st->cur, st->prev);
+        st->step += 1;
+    }
+    return ok();
+}
+
 int sp_wave_run_states(const sp_grid *g, const sp_coeffs *c, double dt, double dx,
                        const sp_grid *gv, const float *v, void *const *states, int64_t n0,
                        int nsteps, const sp_sources *src, const sp_receivers *rec, void *stream) {

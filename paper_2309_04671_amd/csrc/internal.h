@@ -146,4 +146,30 @@ struct SuiteArgs {
 hipError_t launch_suite(int shape, int ndim, int radius, const float *w, const SuiteArgs &a,
                         hipStream_t s);
 
+// Absorbing layer (the PML region): the layer update over up to 7 boxes of
+// the grid.  Pointers at interior (0, 0, 0); u = u^n, prev = u^{n-1} (the
+// output overwrites it), psi updated in place; eta on the same layout with
+// its frame.  Box k covers [x0, x1) x [y0, y1) x [z0, z1).
+struct PmlBox {
+    int x0, x1, y0, y1, z0, z1;
+};
+struct PmlArgs {
+    const float *u;
+    float *prev;
+    const float *v, *eta;
+    float *psi;
+    int nx, ny, nz;
+    int64_t sy, sz;
+    float m_scale, dt, alpha_dt;
+    StarCoef c;
+    SrcList src;
+    int nbox;
+    PmlBox box[7];
+};
+hipError_t launch_pml(const PmlArgs &a, hipStream_t s);
+// eta = eta_max * sum over axes (d_a / width)^2 on every cell of the padded
+// extent, d_a = max(0, width - 1 - a, a - (n_a - width)).
+hipError_t launch_pml_profile(float *eta, int64_t sy, int64_t sz, int nx, int ny, int nz, int width,
+                              float eta_max, hipStream_t s);
+
 }  // namespace sp

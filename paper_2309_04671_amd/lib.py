@@ -26,7 +26,7 @@ ERROR_NAMES = {0: "SP_OK", 1: "SP_EINVAL", 2: "SP_EUNSUPPORTED", 3: "SP_EDEVICE"
 EXPORTS = [
     "sp_grid_init", "sp_grid_init_2d", "sp_stencil_apply", "sp_apply", "sp_wave_meta_bytes", "sp_wave_step",
     "sp_wave_run_states", "sp_wave_adjoint_step", "sp_grad_finish", "sp_energy_ws_bytes",
-    "sp_energy", "sp_shot_bytes", "sp_queue_create", "sp_submit", "sp_poll", "sp_queue_drain",
+    "sp_energy", "sp_pml_profile", "sp_wave_step_pml", "sp_shot_bytes", "sp_queue_create", "sp_submit", "sp_poll", "sp_queue_drain",
     "sp_queue_destroy", "sp_last_error", "sp_version",
 ]
 
@@ -58,6 +58,14 @@ class sp_stencil(ctypes.Structure):
 
 
 SP_STAR, SP_BOX = 0, 1
+
+
+class sp_pml(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("decomposition", ctypes.c_int32),
+                ("alpha", ctypes.c_double), ("eta", ctypes.c_void_p), ("psi", ctypes.c_void_p)]
+
+
+SP_PML_UNIFIED, SP_PML_SEVEN = 0, 1
 
 
 class sp_wave_state(ctypes.Structure):
@@ -125,6 +133,9 @@ def load():
     lib.sp_energy_ws_bytes.argtypes = [P(sp_grid)]
     lib.sp_energy_ws_bytes.restype = i64
     lib.sp_energy.argtypes = [P(sp_grid), P(sp_coeffs), d, d, P(sp_grid), vp, vp, vp, vp, vp, vp]
+    lib.sp_pml_profile.argtypes = [P(sp_grid), i, d, vp, vp]
+    lib.sp_wave_step_pml.argtypes = [P(sp_grid), P(sp_coeffs), d, d, P(sp_grid), vp, P(sp_wave_state), i,
+                                     P(sp_pml), P(sp_sources), P(sp_receivers), vp]
     lib.sp_shot_bytes.argtypes = [P(sp_shot_desc)]
     lib.sp_shot_bytes.restype = i64
     lib.sp_queue_create.argtypes = [P(sp_queue_cfg), P(vp)]
@@ -205,6 +216,22 @@ def sp_apply(g, shape, w, u, v, sweeps=1, stream=None) -> int:
     check(load().sp_apply(ctypes.byref(g), ctypes.byref(st), int(sweeps), ctypes.c_void_p(u),
                           ctypes.c_void_p(v), ctypes.byref(out), stream_ptr(stream)))
     return out.value
+
+
+def sp_pml_profile(gv, width, eta_max, eta_ptr, stream=None):
+    check(load().sp_pml_profile(ctypes.byref(gv), int(width), float(eta_max), ctypes.c_void_p(eta_ptr),
+                                stream_ptr(stream)))
+
+
+def make_pml(width, eta_ptr, psi_ptr, alpha=0.0, decomposition=SP_PML_SEVEN) -> sp_pml:
+    return sp_pml(int(width), int(decomposition), float(alpha), eta_ptr, psi_ptr)
+
+
+def sp_wave_step_pml(g, c, dt, dx, gv, v_ptr, st, nsteps, pml, src=None, rec=None, stream=None):
+    check(load().sp_wave_step_pml(ctypes.byref(g), ctypes.byref(c), float(dt), float(dx), ctypes.byref(gv),
+                                  ctypes.c_void_p(v_ptr), ctypes.byref(st), int(nsteps), ctypes.byref(pml),
+                                  ctypes.byref(src) if src is not None else None,
+                                  ctypes.byref(rec) if rec is not None else None, stream_ptr(stream)))
 
 
 def make_sources(xyz, amp_ptr, amp_stride) -> sp_sources:

@@ -1,0 +1,186 @@
+"""GPU parity of the absorbing layer (sp_wave_step_pml, sp_pml_profile)
+against the FP64 oracle, through the C ABI.
+
+Bars:
+ * profile: within 1e-6 relative of the FP64 profile (FP32 evaluation);
+ * one step from the same state: u and psi rel-L2 <= 1e-5 (both region maps);
+ * multi-step with sources and receivers: rel-L2 <= 1e-4; the seven-region
+   map (inner leapfrog kernel + 6 layer slabs) and the unified map agree to
+   rel-L2 <= 1e-5;
+ * the layer absorbs on the GPU as in the oracle;
+ * bench-size grid: sampled points of one step against oracle windows.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.gpu_util import errors
+
+pytestmark = pytest.mark.gpu
+
+ALPHA = np.pi * 15.0
+
+
+def _setup(nx, ny, nz, W, seed, v=None):
+    from paper_2309_04671_amd import fields, lib
+    g = lib.grid_init(nx, ny, nz)
+    v = synth.layered_velocity(nx, ny, nz, seed) if v is None else v
+    V = fields.Field(g).set_interior(v)
+    dx = 10.0
+    dt = synth.cfl_dt(v, dx)
+    eta = synth.pml_profile(nx, ny, nz, W, synth.pml_eta_max(float(v.max()), W, dx))
+    E = fields.Field(g).set_padded(eta)
+    PSI = fields.Field(g)
+    return g, v, V, dx, dt, eta, E, PSI
+
+
+def test_profile_kernel_matches_the_profile(gpu_lib):
+    from paper_2309_04671_amd import fields, lib
+    for (nx, ny, nz, W) in [(37, 20, 45, 8), (64, 64, 64, 12), (130, 9, 33, 4)]:
+        g = lib.grid_init(nx, ny, nz)
+        E = fields.Field(g)
+        lib.sp_pml_profile(g, W, 123.5, E.ptr)
+        torch.cuda.synchronize()
+        got = E.padded().cpu().numpy().astype(np.float64)
+        ref = synth.pml_profile(nx, ny, nz, W, 123.5)
+        # FP32 evaluation: three squares, two sums and a product
+        assert np.all(np.abs(got - ref) <= 1e-6 * np.abs(ref))
+
+
+@pytest.mark.parametrize("decomp", [0, 1])
+def test_single_step_parity(gpu_lib, decomp):
+    from paper_2309_04671_amd import fields, lib
+    nx, ny, nz, W = 70, 45, 52, 8
+    g, v, V, dx, dt, eta, E, PSI = _setup(nx, ny, nz, W, 3)
+    rng = np.random.default_rng(5)
+    prev = synth.uniform_field((nz, ny, nx), 6)
+    cur = synth.uniform_field((nz, ny, nx), 7)
+    psi = np.zeros((nz + 8, ny + 8, nx + 8))
+    layer = synth.pml_profile(nx, ny, nz, W, 1.0) > 0
+    psi[layer] = rng.uniform(-0.1, 0.1, int(layer.sum()))
+    psi[:4] = psi[-4:] = 0
+    psi[:, :4] = psi[:, -4:] = 0
+    psi[:, :, :4] = psi[:, :, -4:] = 0
+    P, C = fields.Field(g).set_interior(prev), fields.Field(g).set_interior(cur)
+    PSI.set_padded(psi)
+    src = np.array([[3, 20, 30], [35, 22, 26]], np.int32)        # one in the layer, one inside
+    amp = torch.tensor([[5.0, -3.0]], dtype=torch.float32, device="cuda")
+    st = lib.sp_wave_state(C.ptr, P.ptr, None, 0)
+    pml = lib.make_pml(W, E.ptr, PSI.ptr, ALPHA, decomp)
+    lib.sp_wave_step_pml(g, lib.coeffs(synth.star25_coeffs()), dt, dx, g, V.ptr, st, 1, pml,
+                         src=lib.make_sources(src, amp.data_ptr(), 2))
+    torch.cuda.synchronize()
+    r = oracle.wave_pml_run(synth.star25_coeffs(), v, eta, dt, dx, 1, src=src,
+                            amp=amp.cpu().double().numpy(), prev=oracle.padded(prev),
+                            cur=oracle.padded(cur), psi=psi, alpha=ALPHA)
+    e = errors(P.get_interior(), oracle.interior(r["cur"]))
+    ep = errors(PSI.get_interior(), oracle.interior(r["psi"]))
+    print("decomp", decomp, "u", e, "psi", ep)
+    assert e["rel_l2"] <= 1e-5 and ep["rel_l2"] <= 1e-5
+
+
+def _multi(decomp, nx, ny, nz, W, steps):
+    from paper_2309_04671_amd import fields, lib
+    g, v, V, dx, dt, eta, E, PSI = _setup(nx, ny, nz, W, 2)
+    src = np.array([[nx // 2, ny // 3, nz // 2], [2, 2, 2]], np.int32)
+    amp_np = np.stack([synth.ricker(steps, dt), 0.3 * synth.ricker(steps, dt, 25.0)], 1) * 1e3
+    amp = torch.tensor(amp_np, dtype=torch.float32, device="cuda")
+    rec = synth.random_points(nx, ny, nz, 9, 4)
+    rec_d = torch.tensor(rec, device="cuda")
+    tr = torch.zeros((steps, len(rec)), dtype=torch.float32, device="cuda")
+    ws = fields.WaveState(g)
+    pml = lib.make_pml(W, E.ptr, PSI.ptr, ALPHA, decomp)
+    lib.sp_wave_step_pml(g, lib.coeffs(synth.star25_coeffs()), dt, dx, g, V.ptr, ws.st, steps, pml,
+                         src=lib.make_sources(src, amp.data_ptr(), 2),
+                         rec=lib.make_receivers(len(rec), rec_d.data_ptr(), tr.data_ptr(), len(rec)))
+    torch.cuda.synchronize()
+    return (v, eta, dx, dt, src, amp_np, rec), ws.cur().get_interior(), PSI.get_interior(), tr.cpu().numpy()
+
+
+@pytest.mark.parametrize("shape", [(70, 45, 52, 8), (41, 33, 29, 4), (96, 64, 80, 12)])
+def test_multi_step_both_maps_match_the_oracle(gpu_lib, shape):
+    nx, ny, nz, W = shape
+    steps = 80
+    (v, eta, dx, dt, src, amp, rec), u7, p7, t7 = _multi(1, nx, ny, nz, W, steps)
+    _, u1, p1, t1 = _multi(0, nx, ny, nz, W, steps)
+    r = oracle.wave_pml_run(synth.star25_coeffs(), v, eta, dt, dx, steps, src=src, amp=amp, rec=rec,
+                            alpha=ALPHA)
+    ref_u, ref_p = oracle.interior(r["cur"]), oracle.interior(r["psi"])
+    for u, p, t in ((u7, p7, t7), (u1, p1, t1)):
+        assert errors(u, ref_u)["rel_l2"] <= 1e-4
+        assert errors(p, ref_p)["rel_l2"] <= 1e-4
+        assert errors(t, r["traces"])["rel_l2"] <= 1e-4
+    assert errors(u7, u1)["rel_l2"] <= 1e-5 and errors(t7, t1)["rel_l2"] <= 1e-5
+
+
+def test_layer_absorbs_on_the_gpu(gpu_lib):
+    from paper_2309_04671_amd import fields, lib
+    n, W, steps = 48, 12, 500
+    v = np.full((n, n, n), 2000.0)
+    out = {}
+    for on in (True, False):
+        g, v, V, dx, dt, eta, E, PSI = _setup(n, n, n, W, 0, v=v)
+        if not on:
+            E.set_padded(np.zeros_like(eta))
+        amp = torch.tensor(synth.ricker(steps, dt)[:, None] * 1e3, dtype=torch.float32, device="cuda")
+        ws = fields.WaveState(g)
+        lib.sp_wave_step_pml(g, lib.coeffs(synth.star25_coeffs()), dt, dx, g, V.ptr, ws.st, steps,
+                             lib.make_pml(W, E.ptr, PSI.ptr, ALPHA, 1),
+                             src=lib.make_sources([[n // 2] * 3], amp.data_ptr(), 1))
+        torch.cuda.synchronize()
+        u = ws.cur().get_interior().astype(np.float64)[W:-W, W:-W, W:-W]
+        out[on] = float((u ** 2).sum())
+    assert out[False] > 1e6 and out[True] < 1e-4 * out[False]
+
+
+def test_validation(gpu_lib):
+    from paper_2309_04671_amd import fields, lib
+    g = lib.grid_init(40, 40, 40)
+    F = [fields.Field(g) for _ in range(5)]
+    st = lib.sp_wave_state(F[0].ptr, F[1].ptr, None, 0)
+    co = lib.coeffs(synth.star25_coeffs())
+    for W, d, alpha in ((6, 1, 0.0), (20, 1, 0.0), (8, 5, 0.0), (8, 1, -1.0)):
+        with pytest.raises(lib.SpError):
+            lib.sp_wave_step_pml(g, co, 1e-3, 10.0, g, F[2].ptr, st, 1,
+                                 lib.make_pml(W, F[3].ptr, F[4].ptr, alpha, d))
+    with pytest.raises(lib.SpError):      # psi aliasing the output wavefield
+        lib.sp_wave_step_pml(g, co, 1e-3, 10.0, g, F[2].ptr, st, 1, lib.make_pml(8, F[3].ptr, F[1].ptr))
+
+
+def test_bench_size_sampled(gpu_lib):
+    # 512^3 with a 32-cell layer, seven-region map, one step from a random
+    # state: sampled points (layer and inner) against oracle windows
+    from paper_2309_04671_amd import fields, lib
+    n, W = 512, 32
+    g, v, V, dx, dt, eta, E, PSI = _setup(n, n, n, W, 0)
+    gen = torch.Generator().manual_seed(1)
+    P = fields.Field(g).set_interior(torch.rand((n, n, n), generator=gen) - 0.5)
+    C = fields.Field(g).set_interior(torch.rand((n, n, n), generator=gen) - 0.5)
+    ps = torch.rand((n + 8, n + 8, n + 8), generator=gen) * 0.1
+    ps[torch.from_numpy(eta == 0)] = 0
+    PSI.set_padded(ps)
+    before = {k: f.padded().clone() for k, f in (("p", P), ("c", C), ("s", PSI))}
+    st = lib.sp_wave_state(C.ptr, P.ptr, None, 0)
+    lib.sp_wave_step_pml(g, lib.coeffs(synth.star25_coeffs()), dt, dx, g, V.ptr, st, 1,
+                         lib.make_pml(W, E.ptr, PSI.ptr, ALPHA, 1))
+    torch.cuda.synchronize()
+    out_u, out_p = P.padded(), PSI.padded()
+    Vp = V.padded()
+    rng = np.random.default_rng(2)
+    pts = [tuple(int(q) for q in rng.integers(5, n - 5, 3)) for _ in range(120)]
+    pts += [(5, 5, 5), (n - 6, n - 6, n - 6), (W - 1, 200, 300), (W, 200, 300), (200, n - W, 17)]
+    h = 9                                     # window: 11^3 interior + 4-cell frame
+    for z, y, x in pts:
+        sl = tuple(slice(q + 4 - h, q + 4 + h + 1) for q in (z, y, x))
+        sub = lambda t: t[sl].double().cpu().numpy()
+        vw = sub(Vp)[4:-4, 4:-4, 4:-4]
+        r = oracle.wave_pml_run(synth.star25_coeffs(), vw, sub(E.padded()), dt, dx, 1,
+                                prev=sub(before["p"]), cur=sub(before["c"]), psi=sub(before["s"]),
+                                alpha=ALPHA)
+        ref_u, ref_p = r["cur"][h, h, h], r["psi"][h, h, h]
+        got_u, got_p = float(out_u[z + 4, y + 4, x + 4]), float(out_p[z + 4, y + 4, x + 4])
+        assert abs(got_u - ref_u) <= 2e-6 * (1 + abs(ref_u)), (z, y, x, got_u, ref_u)
+        assert abs(got_p - ref_p) <= 2e-6 * (1 + abs(ref_p)), (z, y, x, got_p, ref_p)
