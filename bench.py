@@ -212,24 +212,53 @@ def leg_storage_error(torch, lib, fields, synth, n=128, nt=1000):
     src = np.array([[n // 2, n // 2, n // 2]], np.int32)
     co_d = synth.star25_coeffs()
     t0 = time.perf_counter()
-    ref = oracle.interior(oracle.wave_run(co_d, vel, dt, dx, nt, src=src,
-                                          amp=amp32.astype(np.float64))["cur"])
+    st, chunk = None, 100         # chunks, so that a long run reports progress
+    for k0 in range(0, nt, chunk):
+        k1 = min(nt, k0 + chunk)
+        st = oracle.wave_run(co_d, vel, dt, dx, k1 - k0, src=src,
+                             amp=amp32[k0:k1].astype(np.float64),
+                             prev=None if st is None else st["prev"],
+                             cur=None if st is None else st["cur"])
+        if n > 256:
+            log("oracle %d^3: %d of %d steps" % (n, k1, nt))
+    ref = oracle.interior(st["cur"]).copy()
+    del st
     t_oracle = time.perf_counter() - t0
     gv = lib.grid_init(n, n, n, lib.SP_F32)
     V = fields.Field(gv).set_interior(vel)
     amp = torch.tensor(amp32, device="cuda")
     co = lib.coeffs(co_d)
-    out = {"config": "%d^3, %d steps, vs FP64 oracle (%.1f s on CPU)" % (n, nt, t_oracle)}
+    n_e = min(400, nt)            # the wavelet has died out well before this step
+    out = {"config": "%d^3, %d steps, vs FP64 oracle (%.1f s on CPU); energy drift between steps "
+                     "%d and %d (discrete energy in FP64 on the GPU, source finished)"
+                     % (n, nt, t_oracle, n_e, nt)}
     nref = float(np.linalg.norm(ref))
+    F0, F1 = fields.Field(gv), fields.Field(gv)
+    e_out = torch.zeros(1, dtype=torch.float64, device="cuda")
+    e_ws = torch.zeros(max(int(lib.load().sp_energy_ws_bytes(gv)) // 8, 1), dtype=torch.float64,
+                       device="cuda")
+
+    def energy(ws):
+        # decoded FP32 copies of u^{n-1}, u^n; E between them (FP64 sums)
+        F0.set_interior(ws.decoded("prev"))
+        F1.set_interior(ws.decoded("cur"))
+        lib.sp_energy(gv, co, dt, dx, gv, V.ptr, F0.ptr, F1.ptr, e_out.data_ptr(), e_ws.data_ptr())
+        torch.cuda.synchronize()
+        return float(e_out.item())
+
     for name, dtype in (("fp32", lib.SP_F32), ("fp16_store", lib.SP_F16), ("bf16_store", lib.SP_BF16)):
         g = lib.grid_init(n, n, n, dtype)
         ws = fields.WaveState(g)
-        lib.sp_wave_step(g, co, dt, dx, gv, V.ptr, ws.st, nt,
-                         src=lib.make_sources(src, amp.data_ptr(), 1))
-        torch.cuda.synchronize()
+        srcs = lib.make_sources(src, amp.data_ptr(), 1)
+        lib.sp_wave_step(g, co, dt, dx, gv, V.ptr, ws.st, n_e, src=srcs)
+        e_a = energy(ws)
+        lib.sp_wave_step(g, co, dt, dx, gv, V.ptr, ws.st, nt - n_e, src=srcs)
+        e_b = energy(ws)
         d = ws.decoded() - ref
         out[name] = {"rel_l2": float(np.linalg.norm(d) / nref), "max_abs": float(np.max(np.abs(d))),
-                     "rmsd": float(np.sqrt(np.mean(d * d))), "ref_max": float(np.max(np.abs(ref)))}
+                     "rmsd": float(np.sqrt(np.mean(d * d))), "ref_max": float(np.max(np.abs(ref))),
+                     "energy_drift": float((e_b - e_a) / e_a)}
+        del ws
     return out
 
 
@@ -571,6 +600,9 @@ def main():
     if "storage_error" in legs:
         log("storage error at 128^3 vs the FP64 oracle")
         forms["storage_error_128"] = leg_storage_error(torch, lib, fields, synth)
+    if "storage_error_512" in legs:        # opt-in: about 3 minutes of FP64 oracle on the host
+        log("storage error at 512^3 vs the FP64 oracle")
+        forms["storage_error_512"] = leg_storage_error(torch, lib, fields, synth, n=512)
     if "adjoint" in legs:
         log("adjoint gradient at 256^3")
         forms["adjoint_256"] = leg_adjoint(torch, lib, fields, synth)
