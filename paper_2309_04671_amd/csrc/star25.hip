@@ -120,6 +120,13 @@ __device__ __forceinline__ int xcd_tile(int bid, int n) {
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// Depth of the halo-chunk register queue: the LDS frame of plane z is
+// fetched at iteration z-5, the iteration at which the tiles that own those
+// rows fetch them as their z-queue head, so the shared lines are read from
+// HBM once and found in L2 by the neighbour (fetched one plane ahead, they
+// had left a 4 MB XCD L2 again after the owner's four further planes).
+constexpr int HQ = 5;
+
 // Slabs one block may touch (z-chunk of at most MAX_ZCHUNK_SCALED planes plus
 // the 4-plane margins), for the FP16/BF16 scale tables in LDS.
 constexpr int MAX_BLOCK_SLABS = MAX_ZCHUNK_SCALED / SP_SLAB + 2;
@@ -263,9 +270,12 @@ __device__ __forceinline__ void star25_wave_h(const SweepArgs &a, const int lin)
         }
         nq[j] = ld_ok[j] ? IO::ld(u + (int64_t)(zb + 4) * sz + own[j]) : rzero;
     }
-    raw hv[HPT];
+    raw hq[HPT][HQ];                      // halo chunks of planes z .. z+4
 #pragma unroll
-    for (int j = 0; j < HPT; ++j) hv[j] = h_ok[j] ? IO::ld(u + (int64_t)zb * sz + hoff[j]) : rzero;
+    for (int j = 0; j < HPT; ++j)
+#pragma unroll
+        for (int k = 0; k < HQ; ++k)
+            hq[j][k] = h_ok[j] ? IO::ld(u + (int64_t)(zb + k) * sz + hoff[j]) : rzero;
 
     raw pp[RY];
     f4v vv[RY];
@@ -296,8 +306,11 @@ __device__ __forceinline__ void star25_wave_h(const SweepArgs &a, const int lin)
         }
 #pragma unroll
         for (int j = 0; j < HPT; ++j)
-            if (tid + j * NT < HC) lds[b][hrow[j]][hchk[j]] = hv[j];
+            if (tid + j * NT < HC) lds[b][hrow[j]][hchk[j]] = hq[j][0];
 
+        raw hn[HPT];
+#pragma unroll
+        for (int j = 0; j < HPT; ++j) hn[j] = rzero;
         raw pp_n[RY];
         f4v vv_n[RY];
 #pragma unroll
@@ -311,7 +324,7 @@ __device__ __forceinline__ void star25_wave_h(const SweepArgs &a, const int lin)
                 nq[j] = ld_ok[j] ? IO::ld(u + (int64_t)(z + 5) * sz + own[j]) : rzero;
 #pragma unroll
             for (int j = 0; j < HPT; ++j)
-                hv[j] = h_ok[j] ? IO::ld(u + (int64_t)(z + 1) * sz + hoff[j]) : rzero;
+                hn[j] = h_ok[j] ? IO::ld(u + (int64_t)(z + HQ) * sz + hoff[j]) : rzero;
 #pragma unroll
             for (int j = 0; j < RY; ++j)
                 if (st_ok[j]) {
@@ -419,6 +432,12 @@ __device__ __forceinline__ void star25_wave_h(const SweepArgs &a, const int lin)
             for (int i = 0; i < 8; ++i) q[j][i] = q[j][i + 1];
             pp[j] = pp_n[j];
             vv[j] = vv_n[j];
+        }
+#pragma unroll
+        for (int j = 0; j < HPT; ++j) {
+#pragma unroll
+            for (int k = 0; k + 1 < HQ; ++k) hq[j][k] = hq[j][k + 1];
+            hq[j][HQ - 1] = hn[j];
         }
     }
 }
@@ -559,9 +578,12 @@ __device__ __forceinline__ void star25_body(const SweepArgs &a, const int lin) {
         }
         nq[j] = ld_ok[j] ? IO::ld(u + (int64_t)(zb + 4) * sz + own[j]) : rzero;
     }
-    raw hv[HPT];
+    raw hq[HPT][HQ];                      // halo chunks of planes z .. z+4
 #pragma unroll
-    for (int j = 0; j < HPT; ++j) hv[j] = h_ok[j] ? IO::ld(u + (int64_t)zb * sz + hoff[j]) : rzero;
+    for (int j = 0; j < HPT; ++j)
+#pragma unroll
+        for (int k = 0; k < HQ; ++k)
+            hq[j][k] = h_ok[j] ? IO::ld(u + (int64_t)(zb + k) * sz + hoff[j]) : rzero;
 
     raw pp[RY];
     f4v vv[RY];
@@ -602,8 +624,11 @@ __device__ __forceinline__ void star25_body(const SweepArgs &a, const int lin) {
         }
 #pragma unroll
         for (int j = 0; j < HPT; ++j)
-            if (tid + j * NT < HC) lds[b][hrow[j]][hchk[j]] = IO::dec(hv[j], s0);
+            if (tid + j * NT < HC) lds[b][hrow[j]][hchk[j]] = IO::dec(hq[j][0], s0);
 
+        raw hn[HPT];
+#pragma unroll
+        for (int j = 0; j < HPT; ++j) hn[j] = rzero;
         raw pp_n[RY];
         f4v vv_n[RY];
         d4v gg_n[RY];
@@ -619,7 +644,7 @@ __device__ __forceinline__ void star25_body(const SweepArgs &a, const int lin) {
                 nq[j] = ld_ok[j] ? IO::ld(u + (int64_t)(z + 5) * sz + own[j]) : rzero;
 #pragma unroll
             for (int j = 0; j < HPT; ++j)
-                hv[j] = h_ok[j] ? IO::ld(u + (int64_t)(z + 1) * sz + hoff[j]) : rzero;
+                hn[j] = h_ok[j] ? IO::ld(u + (int64_t)(z + HQ) * sz + hoff[j]) : rzero;
 #pragma unroll
             for (int j = 0; j < RY; ++j)
                 if (st_ok[j]) {
@@ -759,6 +784,12 @@ __device__ __forceinline__ void star25_body(const SweepArgs &a, const int lin) {
             pp[j] = pp_n[j];
             vv[j] = vv_n[j];
             gg[j] = gg_n[j];
+        }
+#pragma unroll
+        for (int j = 0; j < HPT; ++j) {
+#pragma unroll
+            for (int k = 0; k + 1 < HQ; ++k) hq[j][k] = hq[j][k + 1];
+            hq[j][HQ - 1] = hn[j];
         }
     }
 
