@@ -289,6 +289,11 @@ __device__ __forceinline__ void star25_wave_h(const SweepArgs &a, const int lin)
         }
     }
 
+    // this step's source amplitudes, read once per block
+    __shared__ float s_amp[SP_MAX_SOURCES];
+    if (tid < a.src.n) s_amp[tid] = a.src.amp[tid];
+    __syncthreads();
+
     const StarCoef &c = a.c;
     float s_out = 1.f, inv_out = 1.f;
     float tmax = 0.f;
@@ -391,7 +396,7 @@ __device__ __forceinline__ void star25_wave_h(const SweepArgs &a, const int lin)
                     const int d = a.src.x[s] - x;
                     if (d >= 0 && d < 4) {
                         const float vs = vv[j][d];
-                        res[d] += a.src.dt2 * (vs * vs) * a.src.amp[s];
+                        res[d] += a.src.dt2 * (vs * vs) * s_amp[s];
                     }
                 }
             }
@@ -578,22 +583,37 @@ __device__ __forceinline__ void star25_body(const SweepArgs &a, const int lin) {
         }
         nq[j] = ld_ok[j] ? IO::ld(u + (int64_t)(zb + 4) * sz + own[j]) : rzero;
     }
-    raw hq[HPT][HQ];                      // halo chunks of planes z .. z+4
+    // halo chunks of planes z .. z+HD-1; the FP32 leapfrog, gradient and
+    // energy sweeps on 1024-thread blocks (a 128-VGPR budget) keep depth 1
+    constexpr int HD = (NT > 512 && MODE != MODE_APPLY && std::is_same<T, float>::value) ? 1 : HQ;
+    raw hq[HPT][HD];
 #pragma unroll
     for (int j = 0; j < HPT; ++j)
 #pragma unroll
-        for (int k = 0; k < HQ; ++k)
+        for (int k = 0; k < HD; ++k)
             hq[j][k] = h_ok[j] ? IO::ld(u + (int64_t)(zb + k) * sz + hoff[j]) : rzero;
 
-    raw pp[RY];
-    f4v vv[RY];
+    // Single-use streams (u^{n-1}, v) are fetched PF planes ahead: pp/vv hold
+    // plane z, pp1/vv1 plane z+1 when PF = 2 (plane zb+1 <= nz lies in the
+    // frame).  1024-thread blocks (a 128-VGPR budget) and the FP64 gradient
+    // sweep keep PF = 1.
+    constexpr int PF = (NT > 512 || MODE == MODE_GRAD) ? 1 : 2;
+    raw pp[RY], pp1[RY];
+    f4v vv[RY], vv1[RY];
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
         pp[j] = rzero;
         vv[j] = zero;
-        if (PW && st_ok[j]) pp[j] = IO::ld_nt(uprev + (int64_t)zb * sz + own[j]);
-        if ((MODE == MODE_WAVE || MODE == MODE_ENERGY) && st_ok[j])
+        pp1[j] = rzero;
+        vv1[j] = zero;
+        if (PW && st_ok[j]) {
+            pp[j] = IO::ld_nt(uprev + (int64_t)zb * sz + own[j]);
+            if constexpr (PF == 2) pp1[j] = IO::ld_nt(uprev + (int64_t)(zb + 1) * sz + own[j]);
+        }
+        if ((MODE == MODE_WAVE || MODE == MODE_ENERGY) && st_ok[j]) {
             vv[j] = ld4_nt(a.v + (int64_t)zb * a.vsz + vown[j]);
+            if constexpr (PF == 2) vv1[j] = ld4_nt(a.v + (int64_t)(zb + 1) * a.vsz + vown[j]);
+        }
     }
     d4v gg[RY];
 #pragma unroll
@@ -603,6 +623,12 @@ __device__ __forceinline__ void star25_body(const SweepArgs &a, const int lin) {
             gg[j] = *reinterpret_cast<const d4v *>(a.gacc + (int64_t)zb * sz + own[j]);
     }
     double esum = 0.0;                    // MODE_ENERGY: this thread's partial sum
+
+    // this step's source amplitudes, read once per block: a global load in
+    // the plane loop would wait for every outstanding prefetch
+    __shared__ float s_amp[SP_MAX_SOURCES];
+    if (tid < a.src.n) s_amp[tid] = a.src.amp[tid];
+    __syncthreads();
 
     const StarCoef &c = a.c;
     float s_out = 1.f, inv_out = 1.f;     // output scale of the current slab
@@ -644,13 +670,13 @@ __device__ __forceinline__ void star25_body(const SweepArgs &a, const int lin) {
                 nq[j] = ld_ok[j] ? IO::ld(u + (int64_t)(z + 5) * sz + own[j]) : rzero;
 #pragma unroll
             for (int j = 0; j < HPT; ++j)
-                hn[j] = h_ok[j] ? IO::ld(u + (int64_t)(z + HQ) * sz + hoff[j]) : rzero;
+                hn[j] = h_ok[j] ? IO::ld(u + (int64_t)(z + HD) * sz + hoff[j]) : rzero;
 #pragma unroll
             for (int j = 0; j < RY; ++j)
                 if (st_ok[j]) {
-                    if (PW) pp_n[j] = IO::ld_nt(uprev + (int64_t)(z + 1) * sz + own[j]);
+                    if (PW) pp_n[j] = IO::ld_nt(uprev + (int64_t)(z + PF) * sz + own[j]);
                     if (MODE == MODE_WAVE || MODE == MODE_ENERGY)
-                        vv_n[j] = ld4_nt(a.v + (int64_t)(z + 1) * a.vsz + vown[j]);
+                        vv_n[j] = ld4_nt(a.v + (int64_t)(z + PF) * a.vsz + vown[j]);
                     if (MODE == MODE_GRAD)
                         gg_n[j] = __builtin_nontemporal_load(
                             reinterpret_cast<const d4v *>(a.gacc + (int64_t)(z + 1) * sz + own[j]));
@@ -698,7 +724,7 @@ __device__ __forceinline__ void star25_body(const SweepArgs &a, const int lin) {
                         const int d = a.src.x[s] - x;
                         if (d >= 0 && d < 4) {
                             const float vs = vv[j][d];
-                            res[d] += a.src.dt2 * (vs * vs) * a.src.amp[s];
+                            res[d] += a.src.dt2 * (vs * vs) * s_amp[s];
                         }
                     }
                 }
@@ -709,7 +735,7 @@ __device__ __forceinline__ void star25_body(const SweepArgs &a, const int lin) {
                 for (int s = 0; s < a.src.n; ++s) {
                     if (a.src.z[s] == z && a.src.y[s] == y) {
                         const int d = a.src.x[s] - x;
-                        if (d >= 0 && d < 4) term[d] += a.dx2 * a.src.amp[s];
+                        if (d >= 0 && d < 4) term[d] += a.dx2 * s_amp[s];
                     }
                 }
                 if (st_ok[j]) {
@@ -781,15 +807,22 @@ __device__ __forceinline__ void star25_body(const SweepArgs &a, const int lin) {
         for (int j = 0; j < RY; ++j) {
 #pragma unroll
             for (int i = 0; i < 8; ++i) q[j][i] = q[j][i + 1];
-            pp[j] = pp_n[j];
-            vv[j] = vv_n[j];
+            if constexpr (PF == 2) {
+                pp[j] = pp1[j];
+                vv[j] = vv1[j];
+                pp1[j] = pp_n[j];
+                vv1[j] = vv_n[j];
+            } else {
+                pp[j] = pp_n[j];
+                vv[j] = vv_n[j];
+            }
             gg[j] = gg_n[j];
         }
 #pragma unroll
         for (int j = 0; j < HPT; ++j) {
 #pragma unroll
-            for (int k = 0; k + 1 < HQ; ++k) hq[j][k] = hq[j][k + 1];
-            hq[j][HQ - 1] = hn[j];
+            for (int k = 0; k + 1 < HD; ++k) hq[j][k] = hq[j][k + 1];
+            hq[j][HD - 1] = hn[j];
         }
     }
 
