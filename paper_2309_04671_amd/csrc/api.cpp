@@ -425,50 +425,52 @@ int sp_wave_step_pml(const sp_grid *g, const sp_coeffs *c, double dt, double dx,
     if (g->pitch_x * g->pitch_y >= ((int64_t)1 << 31))
         return fail(SP_EUNSUPPORTED, "%s: planes of 2^31 or more elements", who);
 
-    // layer kernel arguments (whole-grid coordinates)
-    sp::PmlArgs pa;
-    std::memset(&pa, 0, sizeof pa);
-    pa.v = v + gv->origin;
-    pa.eta = pml->eta + gv->origin;
-    pa.psi = pml->psi + g->origin;
-    pa.nx = nx;
-    pa.ny = ny;
-    pa.nz = nz;
-    pa.sy = a.sy;
-    pa.sz = a.sz;
-    pa.m_scale = a.m_scale;
-    pa.dt = (float)dt;
-    pa.alpha_dt = (float)(pml->alpha * dt);
-    pa.c = a.c;
-    pa.src = a.src;
-    if (!seven) {
-        pa.nbox = 1;
-        pa.box[0] = {0, nx, 0, ny, 0, nz};
-    } else {
-        pa.nbox = 6;
-        pa.box[0] = {0, nx, 0, ny, 0, W};
-        pa.box[1] = {0, nx, 0, ny, nz - W, nz};
-        pa.box[2] = {0, nx, 0, W, W, nz - W};
-        pa.box[3] = {0, nx, ny - W, ny, W, nz - W};
-        pa.box[4] = {0, W, W, ny - W, W, nz - W};
-        pa.box[5] = {nx - W, nx, W, ny - W, W, nz - W};
-    }
-    // inner box: the streaming leapfrog kernel on the sub-grid [W, n - W)^3
-    sp::SweepArgs ai = a;
-    sp::TileCfg ti{};
-    const int64_t shift = (int64_t)W * (a.sz + a.sy + 1);
-    if (seven) {
-        ai.nx = nx - 2 * W;
-        ai.ny = ny - 2 * W;
-        ai.nz = nz - 2 * W;
-        ai.v = a.v + shift;
-        for (int q = 0; q < ai.src.n; ++q) {   // sources outside the box never match a point
-            ai.src.x[q] -= W;
-            ai.src.y[q] -= W;
-            ai.src.z[q] -= W;
+    // Boxes [x0, x1) x [y0, y1) x [z0, z1), each swept by k_star25 on a
+    // sub-grid whose pointers are offset to the box corner (its halo being
+    // the neighbouring cells of the full grid).  x0 must stay a multiple of 4
+    // (16-byte rows), so the inner box ends at a multiple of 4 and the high x
+    // slab takes the remainder: its extra cells have eta = 0 and the layer
+    // update reduces to the leapfrog there.
+    struct Box {
+        int mode;
+        sp::SweepArgs a;
+        sp::TileCfg t;
+        int64_t off;
+    };
+    Box boxes[7];
+    int nb = 0;
+    auto add = [&](int x0, int x1, int y0, int y1, int z0, int z1, int mode) {
+        Box &b = boxes[nb++];
+        b.mode = mode;
+        b.a = a;
+        b.a.nx = x1 - x0;
+        b.a.ny = y1 - y0;
+        b.a.nz = z1 - z0;
+        b.off = (int64_t)z0 * a.sz + (int64_t)y0 * a.sy + x0;
+        b.a.v = a.v + b.off;
+        b.a.eta = pml->eta + gv->origin + b.off;
+        b.a.psi = pml->psi + g->origin + b.off;
+        b.a.dt = (float)dt;
+        b.a.alpha_dt = (float)(pml->alpha * dt);
+        for (int q = 0; q < b.a.src.n; ++q) {   // sources outside the box never match a point
+            b.a.src.x[q] -= x0;
+            b.a.src.y[q] -= y0;
+            b.a.src.z[q] -= z0;
         }
-        ti = sp::choose_tiles(ai.nx, ai.ny, ai.nz, SP_F32, sp::MODE_WAVE);
-        fill_tiling(ai, ti);
+        b.t = sp::choose_tiles(b.a.nx, b.a.ny, b.a.nz, SP_F32, mode);
+        fill_tiling(b.a, b.t);
+    };
+    if (!seven) {
+        add(0, nx, 0, ny, 0, nz, sp::MODE_PML);
+    } else {
+        const int xe = W + 4 * ((nx - 2 * W) / 4);
+        add(W, xe, W, ny - W, W, nz - W, sp::MODE_WAVE);
+        add(0, nx, 0, ny, 0, W, sp::MODE_PML);
+        add(0, nx, 0, ny, nz - W, nz, sp::MODE_PML);
+        add(0, nx, 0, W, W, nz - W, sp::MODE_PML);
+        add(0, nx, ny - W, ny, W, nz - W, sp::MODE_PML);
+        add(0, W, W, ny - W, W, nz - W, sp::MODE_PML);
+        add(xe, nx, W, ny - W, W, nz - W, sp::MODE_PML);
     }
     const int nrec = rec ? rec->n : 0;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -479,17 +481,14 @@ int sp_wave_step_pml(const sp_grid *g, const sp_coeffs *c, double dt, double dx,
         float *prev = static_cast<float *>(st->prev) + g->origin;
         const float *amp = a.src.n ? src->amp + n * src->amp_stride : nullptr;
         hipError_t err = hipSuccess;
-        if (seven) {
-            ai.u = cur + shift;
-            ai.prev = prev + shift;
-            ai.out = prev + shift;
-            ai.src.amp = amp;
-            err = sp::launch_sweep(sp::MODE_WAVE, SP_F32, ti, ai, s);
+        for (int q = 0; q < nb && err == hipSuccess; ++q) {
+            Box &b = boxes[q];
+            b.a.u = cur + b.off;
+            b.a.prev = prev + b.off;
+            b.a.out = prev + b.off;
+            b.a.src.amp = amp;
+            err = sp::launch_sweep(b.mode, SP_F32, b.t, b.a, s);
         }
-        pa.u = cur;
-        pa.prev = prev;
-        pa.src.amp = amp;
-        if (err == hipSuccess) err = sp::launch_pml(pa, s);
         if (err == hipSuccess && nrec > 0)
             err = sp::launch_record(SP_F32, prev, nullptr, a.sy, a.sz, nx, ny, nz, rec->xyz, nrec,
                                     rec->traces + (n - step0) * rec->trace_stride, s);

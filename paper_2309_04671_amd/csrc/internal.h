@@ -14,6 +14,7 @@ enum Mode : int {
     MODE_WAVE = 1,    // out = 2u - prev + m L u (+ sources)
     MODE_GRAD = 2,    // G += w * (L u + dx^2 f e_src)      (FP64 G; w in `prev`)
     MODE_ENERGY = 3,  // partial[block] = sum (w - u)^2 / m - w L u   (FP64; w in `prev`)
+    MODE_PML = 4,     // absorbing-layer leapfrog (damping eta, auxiliary psi; FP32)
 };
 
 // Stencil weights rounded once to FP32 (paper Eq. 3).
@@ -63,6 +64,9 @@ struct SweepArgs {
     SlabMeta meta;       // FP16/BF16 storage only
     double *gacc;        // MODE_GRAD: FP64 field on the FP32 layout; MODE_ENERGY: partial sums
     float dx2;           // MODE_GRAD: dx^2 (source term)
+    const float *eta;    // MODE_PML: damping (1/s) on v's layout, frame included
+    float *psi;          // MODE_PML: auxiliary field on u's layout, updated in place
+    float dt, alpha_dt;  // MODE_PML: time step and frequency shift times dt
     int tiles_x, tiles_y, zchunk, nzc;
 };
 
@@ -146,27 +150,6 @@ struct SuiteArgs {
 hipError_t launch_suite(int shape, int ndim, int radius, const float *w, const SuiteArgs &a,
                         hipStream_t s);
 
-// Absorbing layer (the PML region): the layer update over up to 7 boxes of
-// the grid.  Pointers at interior (0, 0, 0); u = u^n, prev = u^{n-1} (the
-// output overwrites it), psi updated in place; eta on the same layout with
-// its frame.  Box k covers [x0, x1) x [y0, y1) x [z0, z1).
-struct PmlBox {
-    int x0, x1, y0, y1, z0, z1;
-};
-struct PmlArgs {
-    const float *u;
-    float *prev;
-    const float *v, *eta;
-    float *psi;
-    int nx, ny, nz;
-    int64_t sy, sz;
-    float m_scale, dt, alpha_dt;
-    StarCoef c;
-    SrcList src;
-    int nbox;
-    PmlBox box[7];
-};
-hipError_t launch_pml(const PmlArgs &a, hipStream_t s);
 // eta = eta_max * sum over axes (d_a / width)^2 on every cell of the padded
 // extent, d_a = max(0, width - 1 - a, a - (n_a - width)).
 hipError_t launch_pml_profile(float *eta, int64_t sy, int64_t sz, int nx, int ny, int nz, int width,

@@ -100,6 +100,8 @@ template <> struct Io<__bf16> {
     }
 };
 
+__device__ __forceinline__ f4v ld4(const float *p) { return *reinterpret_cast<const f4v *>(p); }
+
 __device__ __forceinline__ f4v ld4_nt(const float *p) {
     return __builtin_nontemporal_load(reinterpret_cast<const f4v *>(p));
 }
@@ -467,8 +469,11 @@ __device__ __forceinline__ void star25_body(const SweepArgs &a, const int lin) {
     constexpr int HPT = (HC + NT - 1) / NT;
     static_assert(TY % RY == 0, "RY must divide TY");
     static_assert(MODE == MODE_WAVE || !IO::scaled, "only the leapfrog step has FP16/BF16 storage");
+    static_assert(MODE != MODE_PML || RY == 1, "the absorbing-layer mode runs one row per thread");
+    constexpr bool VW = (MODE == MODE_WAVE || MODE == MODE_ENERGY || MODE == MODE_PML);  // reads v
     typedef double d4v __attribute__((ext_vector_type(4)));
-    constexpr bool PW = (MODE == MODE_WAVE || MODE == MODE_GRAD || MODE == MODE_ENERGY);  // reads `prev`
+    constexpr bool PW = (MODE == MODE_WAVE || MODE == MODE_GRAD || MODE == MODE_ENERGY ||
+                         MODE == MODE_PML);  // reads `prev`
     __shared__ f4v lds[2][LR][LC];
 
     const int tix = lin % a.tiles_x;
@@ -597,7 +602,7 @@ __device__ __forceinline__ void star25_body(const SweepArgs &a, const int lin) {
     // plane z, pp1/vv1 plane z+1 when PF = 2 (plane zb+1 <= nz lies in the
     // frame).  1024-thread blocks (a 128-VGPR budget) and the FP64 gradient
     // sweep keep PF = 1.
-    constexpr int PF = (NT > 512 || MODE == MODE_GRAD) ? 1 : 2;
+    constexpr int PF = (NT > 512 || MODE == MODE_GRAD || MODE == MODE_PML) ? 1 : 2;
     raw pp[RY], pp1[RY];
     f4v vv[RY], vv1[RY];
 #pragma unroll
@@ -610,7 +615,7 @@ __device__ __forceinline__ void star25_body(const SweepArgs &a, const int lin) {
             pp[j] = IO::ld_nt(uprev + (int64_t)zb * sz + own[j]);
             if constexpr (PF == 2) pp1[j] = IO::ld_nt(uprev + (int64_t)(zb + 1) * sz + own[j]);
         }
-        if ((MODE == MODE_WAVE || MODE == MODE_ENERGY) && st_ok[j]) {
+        if (VW && st_ok[j]) {
             vv[j] = ld4_nt(a.v + (int64_t)zb * a.vsz + vown[j]);
             if constexpr (PF == 2) vv1[j] = ld4_nt(a.v + (int64_t)(zb + 1) * a.vsz + vown[j]);
         }
@@ -623,6 +628,26 @@ __device__ __forceinline__ void star25_body(const SweepArgs &a, const int lin) {
             gg[j] = *reinterpret_cast<const d4v *>(a.gacc + (int64_t)zb * sz + own[j]);
     }
     double esum = 0.0;                    // MODE_ENERGY: this thread's partial sum
+
+    // MODE_PML (one row per thread): damping eta as a 3-plane queue of the
+    // own chunk (planes z-1, z, z+1) plus the x/y-neighbour chunks of plane
+    // z (x-4, x+4, y-1, y+1); psi of plane z.  All fetched one plane ahead
+    // from offsets that are valid for every lane.
+    f4v eq[3], ex[4], ps;
+    const int64_t ve = st_ok[0] ? vown[0] : 0, pe = st_ok[0] ? own[0] : 0;
+    auto eta_xy = [&](int zz, f4v *d) {
+        const float *e = a.eta + (int64_t)zz * a.vsz + ve;
+        d[0] = ld4(e - 4);
+        d[1] = ld4(e + 4);
+        d[2] = ld4(e - a.vsy);
+        d[3] = ld4(e + a.vsy);
+    };
+    if constexpr (MODE == MODE_PML) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) eq[k] = ld4(a.eta + (int64_t)(zb - 1 + k) * a.vsz + ve);
+        eta_xy(zb, ex);
+        ps = ld4(a.psi + (int64_t)zb * sz + pe);
+    }
 
     // this step's source amplitudes, read once per block: a global load in
     // the plane loop would wait for every outstanding prefetch
@@ -675,12 +700,18 @@ __device__ __forceinline__ void star25_body(const SweepArgs &a, const int lin) {
             for (int j = 0; j < RY; ++j)
                 if (st_ok[j]) {
                     if (PW) pp_n[j] = IO::ld_nt(uprev + (int64_t)(z + PF) * sz + own[j]);
-                    if (MODE == MODE_WAVE || MODE == MODE_ENERGY)
-                        vv_n[j] = ld4_nt(a.v + (int64_t)(z + PF) * a.vsz + vown[j]);
+                    if (VW) vv_n[j] = ld4_nt(a.v + (int64_t)(z + PF) * a.vsz + vown[j]);
                     if (MODE == MODE_GRAD)
                         gg_n[j] = __builtin_nontemporal_load(
                             reinterpret_cast<const d4v *>(a.gacc + (int64_t)(z + 1) * sz + own[j]));
                 }
+        }
+        f4v eq_n, ex_n[4], ps_n;
+        if constexpr (MODE == MODE_PML) {
+            // planes z+2 (<= nz+1) and z+1 always lie in the frame
+            eq_n = ld4(a.eta + (int64_t)(z + 2) * a.vsz + ve);
+            eta_xy(z + 1, ex_n);
+            ps_n = ld4(a.psi + (int64_t)(z + 1) * sz + pe);
         }
 
         lds_barrier();
@@ -726,6 +757,44 @@ __device__ __forceinline__ void star25_body(const SweepArgs &a, const int lin) {
                             const float vs = vv[j][d];
                             res[d] += a.src.dt2 * (vs * vs) * s_amp[s];
                         }
+                    }
+                }
+            } else if (MODE == MODE_PML) {
+                // layer update (see the absorbing-layer equations): acc = L u
+                const f4v L = lds[b][ly * RY + j + 4][lx], R = lds[b][ly * RY + j + 4][lx + 2];
+                const f4v eC = eq[1];
+                f4v pn;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float ux = (i < 3 ? ctr[i + 1] : R[0]) - (i > 0 ? ctr[i - 1] : L[3]);
+                    const float ex1 = (i < 3 ? eC[i + 1] : ex[1][0]) - (i > 0 ? eC[i - 1] : ex[0][3]);
+                    const float G = 0.25f * (ex1 * ux + (ex[3][i] - ex[2][i]) * (yrow[j + 5][i] - yrow[j + 3][i]) +
+                                             (eq[2][i] - eq[0][i]) * (q[j][5][i] - q[j][3][i]));
+                    const float ae = eC[i] * a.dt;
+                    const float bb = ae + a.alpha_dt;
+                    pn[i] = ((1.f - 0.5f * bb) * ps[i] - a.dt * G) / (1.f + 0.5f * bb);
+                    const float m = vv[j][i] * vv[j][i] * a.m_scale;
+                    res[i] = ((2.f - ae * ae) * ctr[i] - (1.f - ae) * IO::dec(pp[j], 1.f)[i] +
+                              m * (acc[i] + 0.5f * (ps[i] + pn[i]))) / (1.f + ae);
+                }
+                const int y = ybase + j;
+                for (int s = 0; s < a.src.n; ++s) {
+                    if (a.src.z[s] == z && a.src.y[s] == y) {
+                        const int d = a.src.x[s] - x;
+                        if (d >= 0 && d < 4) {
+                            const float vs = vv[j][d];
+                            res[d] += a.src.dt2 * (vs * vs) * s_amp[s];
+                        }
+                    }
+                }
+                if (st_ok[j]) {
+                    float *po = a.psi + (int64_t)z * sz + own[j];
+                    if (x + 4 <= a.nx) {
+                        *reinterpret_cast<f4v *>(po) = pn;
+                    } else {
+                        po[0] = pn[0];
+                        if (x + 1 < a.nx) po[1] = pn[1];
+                        if (x + 2 < a.nx) po[2] = pn[2];
                     }
                 }
             } else if (MODE == MODE_GRAD) {
@@ -817,6 +886,14 @@ __device__ __forceinline__ void star25_body(const SweepArgs &a, const int lin) {
                 vv[j] = vv_n[j];
             }
             gg[j] = gg_n[j];
+        }
+        if constexpr (MODE == MODE_PML) {
+            eq[0] = eq[1];
+            eq[1] = eq[2];
+            eq[2] = eq_n;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) ex[k] = ex_n[k];
+            ps = ps_n;
         }
 #pragma unroll
         for (int j = 0; j < HPT; ++j) {
@@ -964,6 +1041,12 @@ hipError_t launch_t(int mode, const SweepArgs &a, hipStream_t s) {
     const dim3 grid(nblk), block((TX / 4) * (TY / RY));
     if (mode == MODE_WAVE) {
         hipLaunchKernelGGL((k_star25<TX, TY, RY, MODE_WAVE, T>), grid, block, 0, s, a);
+    } else if (mode == MODE_PML) {
+        // the absorbing layer: FP32, one row per thread, 512 or 256 threads
+        if constexpr (std::is_same<T, float>::value && RY == 1 && TX * TY / 4 <= 512)
+            hipLaunchKernelGGL((k_star25<TX, TY, RY, MODE_PML, T>), grid, block, 0, s, a);
+        else
+            return hipErrorInvalidValue;
     } else {
         if constexpr (Io<T>::scaled) {
             return hipErrorInvalidValue;
@@ -1017,7 +1100,9 @@ TileCfg choose_tiles(int nx, int ny, int nz, int dtype, int mode) {
     //    256x16x1 tiles at four waves per SIMD (about 512 blocks) where the
     //    grid has at least two of them across x, else the FP16 choice;
     //  * the FP32 APPLY sweep (8 B per point) runs best on 256x16x1 tiles
-    //    too, but with one long z-chunk per tile (about 256 blocks).
+    //    too, but with one long z-chunk per tile (about 256 blocks);
+    //  * the absorbing-layer mode runs one row per thread in 512-thread
+    //    256x8x1 tiles (64x16x1 for narrow boxes).
     // z-chunks are at least 16 planes (each chunk re-reads 8 planes of u,
     // mostly from L2).  These targets are measured optima on MI355X.
     struct Cand {
@@ -1027,9 +1112,11 @@ TileCfg choose_tiles(int nx, int ny, int nz, int dtype, int mode) {
     static const Cand c16[3] = {{128, 16, 2, 4096, 1}, {128, 16, 2, 4096, 1}, {64, 16, 1, 4096, 1}};
     static const Cand cbf[3] = {{256, 16, 1, 512, 2}, {128, 16, 2, 4096, 1}, {64, 16, 1, 4096, 1}};
     static const Cand cap[3] = {{256, 16, 1, 256, 2}, {128, 16, 2, 512, 1}, {64, 16, 1, 512, 1}};
+    static const Cand cpm[3] = {{256, 8, 1, 512, 1}, {256, 8, 1, 512, 1}, {64, 16, 1, 512, 1}};
     const Cand *cand = dtype == SP_F16    ? c16
                        : dtype == SP_BF16 ? cbf
                        : mode == MODE_APPLY ? cap
+                       : mode == MODE_PML   ? cpm
                                             : c32;
     TileCfg t;
     int want = 256;
