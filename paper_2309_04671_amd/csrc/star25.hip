@@ -1073,6 +1073,17 @@ hipError_t launch_cfg(int mode, const TileCfg &t, const SweepArgs &a, hipStream_
     if (t.tx == 256 && t.ty == 8 && t.ry == 2) return launch_t<256, 8, 2, T>(mode, a, s);
     if (t.tx == 256 && t.ty == 16 && t.ry == 1) return launch_t<256, 16, 1, T>(mode, a, s);
     if (t.tx == 256 && t.ty == 8 && t.ry == 1) return launch_t<256, 8, 1, T>(mode, a, s);
+    if (t.tx == 32 && t.ty == 32 && t.ry == 1) {
+        // the absorbing layer's x slabs: one 128-byte line per tile row
+        if constexpr (std::is_same<T, float>::value) {
+            if (mode == MODE_PML) {
+                const dim3 grid(a.tiles_x * a.tiles_y * a.nzc), block(256);
+                hipLaunchKernelGGL((k_star25<32, 32, 1, MODE_PML, float>), grid, block, 0, s, a);
+                return hipGetLastError();
+            }
+        }
+        return hipErrorInvalidValue;
+    }
     return hipErrorInvalidValue;
 }
 
@@ -1102,7 +1113,7 @@ TileCfg choose_tiles(int nx, int ny, int nz, int dtype, int mode) {
     //  * the FP32 APPLY sweep (8 B per point) runs best on 256x16x1 tiles
     //    too, but with one long z-chunk per tile (about 256 blocks);
     //  * the absorbing-layer mode runs one row per thread in 512-thread
-    //    256x8x1 tiles (64x16x1 for narrow boxes).
+    //    256x8x1 tiles, 64x16x1 or 32x32x1 for narrow boxes (the x slabs).
     // z-chunks are at least 16 planes (each chunk re-reads 8 planes of u,
     // mostly from L2).  These targets are measured optima on MI355X.
     struct Cand {
@@ -1112,7 +1123,7 @@ TileCfg choose_tiles(int nx, int ny, int nz, int dtype, int mode) {
     static const Cand c16[3] = {{128, 16, 2, 4096, 1}, {128, 16, 2, 4096, 1}, {64, 16, 1, 4096, 1}};
     static const Cand cbf[3] = {{256, 16, 1, 512, 2}, {128, 16, 2, 4096, 1}, {64, 16, 1, 4096, 1}};
     static const Cand cap[3] = {{256, 16, 1, 256, 2}, {128, 16, 2, 512, 1}, {64, 16, 1, 512, 1}};
-    static const Cand cpm[3] = {{256, 8, 1, 512, 1}, {256, 8, 1, 512, 1}, {64, 16, 1, 512, 1}};
+    static const Cand cpm[3] = {{256, 8, 1, 512, 1}, {64, 16, 1, 512, 1}, {32, 32, 1, 512, 1}};
     const Cand *cand = dtype == SP_F16    ? c16
                        : dtype == SP_BF16 ? cbf
                        : mode == MODE_APPLY ? cap
