@@ -36,10 +36,12 @@ def log(msg):
 
 
 def kernel_source_hash() -> str:
-    """Hash of the source that defines the timed kernel and its tile choice."""
+    """Hash of the sources that define the timed kernel, its helpers, its
+    argument layout and its tile choice."""
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2309_04671_amd", "csrc", "star25.hip"), "rb") as fh:
-        h.update(fh.read())
+    for name in ("star25.hip", "kcommon.h", "internal.h"):
+        with open(os.path.join(ROOT, "paper_2309_04671_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -313,6 +315,54 @@ def leg_adjoint(torch, lib, fields, synth, n=256, nt=1000, ckpt=32):
 
 
 
+def leg_fused(torch, lib, fields, synth, nt=100):
+    """Two leapfrog steps per sweep (sp_wave_step_fused) against the
+    single-step sweep on the 1024x1024x512 workload, nt steps each after a
+    warm-up run, median of 3.  Reported as effective bytes: the single-step
+    algorithmic 16 B per point-step over the measured time, and the fused
+    sweep's own 10 B per point-step (u^n, u^{n-1}, v read once, u^{n+1} and
+    u^{n+2} written, per two steps)."""
+    nx, ny, nz = NX, NY, NZ
+    g = lib.grid_init(nx, ny, nz)
+    v = synth.layered_velocity(nx, ny, nz, 0)
+    V = fields.Field(g).set_interior(v)
+    dx = 10.0
+    dt = synth.cfl_dt(v, dx)
+    del v
+    amp = torch.tensor(synth.ricker(nt, dt)[:, None], dtype=torch.float32, device="cuda")
+    src = lib.make_sources([[nx // 2, ny // 2, nz // 2]], amp.data_ptr(), 1)
+    co = lib.coeffs(synth.star25_coeffs())
+    ws = fields.WaveState(g, spares=True)
+    stream = torch.cuda.current_stream()
+    runs = {"single_step": lambda: lib.sp_wave_step(g, co, dt, dx, g, V.ptr, ws.st, nt, src=src,
+                                                    stream=stream),
+            "fused_two_steps": lambda: lib.sp_wave_step_fused(g, co, dt, dx, g, V.ptr, ws.st, nt,
+                                                              ws.spare, src=src, stream=stream)}
+    out = {}
+    pts = nx * ny * nz
+    for name, fn in runs.items():
+        ws.reset()
+        fn()
+        ms = []
+        for _ in range(3):
+            ws.reset()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1) / nt)
+        m = sorted(ms)[1]
+        out[name] = {"us_per_step": round(m * 1e3, 1), "gpts": round(pts / m / 1e6, 1),
+                     "effective_gbs_at_16B": round(16 * pts / m / 1e6, 1)}
+    f = out["fused_two_steps"]
+    f["algorithmic_gbs_at_10B"] = round(10 * pts / (f["us_per_step"] * 1e3), 1)
+    f["vs_single_step"] = round(out["single_step"]["us_per_step"] / f["us_per_step"], 3)
+    out["config"] = "1024x1024x512, %d steps, 64x48 regions (56x40 tiles), median of 3" % nt
+    del ws, V
+    return out
+
+
 def leg_pml(torch, lib, fields, synth, nt=100, width=32):
     """Leapfrog with the absorbing layer on the 1024x1024x512 workload (layer
     of `width` cells on every face): the seven-region map (inner box by the
@@ -480,7 +530,7 @@ def main():
                     help="override the headline grid (profiling runs only)")
     ap.add_argument("--no-headline", action="store_true",
                     help="skip the headline run (profiling runs of the extra legs)")
-    ap.add_argument("--legs", default="storage,storage_error,adjoint,pml,suite,serve",
+    ap.add_argument("--legs", default="storage,storage_error,adjoint,fused,pml,suite,serve",
                     help="extra measurements after the headline run (comma list; '' for none)")
     ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
                     help="instead of the benchmark, copy a GIB-sized buffer 4 times with torch "
@@ -590,7 +640,7 @@ def main():
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
-                     "avg_launch_us": round(launch_s * 1e6, 2),
+                     "avg_launch_us": round(launch_s * 1e6, 2) if ev else None,
                      "bytes_per_launch": bpp * npts},
         "hbm_frac_of_wall": round(gpts * BYTES_PER_POINT / HBM_PEAK_GBS, 4),
         "gflops": round(gpts * FLOPS_PER_POINT, 1),
@@ -611,6 +661,10 @@ def main():
     if "adjoint" in legs:
         log("adjoint gradient at 256^3")
         forms["adjoint_256"] = leg_adjoint(torch, lib, fields, synth)
+    if "fused" in legs:
+        log("two steps per sweep")
+        forms["fused"] = leg_fused(torch, lib, fields, synth)
+        torch.cuda.empty_cache()
     if "pml" in legs:
         log("absorbing layer")
         forms["pml"] = leg_pml(torch, lib, fields, synth)

@@ -212,6 +212,24 @@ int sp_wave_step(const sp_grid *g, const sp_coeffs *c, double dt, double dx,
                  const sp_sources *src, const sp_receivers *rec, void *stream);
 
 /*
+ * sp_wave_step_fused -- the same `nsteps` steps as sp_wave_step (FP32 grids
+ * only), two per sweep over the grid: temporal blocking, which the paper
+ * lists among the tuning dimensions of its GPU tilings.  Each sweep reads
+ * u^n, u^{n-1} and v once and writes u^{n+1} and u^{n+2} (20 B per point
+ * for two steps instead of 32); an odd last step runs the single-step
+ * sweep.  Results, sources and receivers are those of sp_wave_step.
+ *
+ * spare is a HOST array of two DEVICE fields on grid g, distinct from each
+ * other and from the state's fields, with zero halos (allocate them zeroed);
+ * their interiors are overwritten.  On return the state points at the two
+ * newest fields and spare[0], spare[1] at the other two.
+ */
+int sp_wave_step_fused(const sp_grid *g, const sp_coeffs *c, double dt, double dx,
+                       const sp_grid *gv, const float *v, sp_wave_state *st, int nsteps,
+                       void **spare, const sp_sources *src, const sp_receivers *rec,
+                       void *stream);
+
+/*
  * sp_wave_run_states -- leapfrog steps that keep every state (FP32 grids
  * only): the recompute primitive of checkpointed adjoints.  states is a HOST
  * array of nsteps+2 DEVICE field pointers (grid g): states[0] = u^{n0-1} and

@@ -12,7 +12,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB_PATH = os.path.join(PKG, "libstencil.so")
 
-SOURCES = ["star25.hip", "suite.hip", "pml.hip", "api.cpp", "queue.cpp"]
+SOURCES = ["star25.hip", "tb2.hip", "suite.hip", "pml.hip", "api.cpp", "queue.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

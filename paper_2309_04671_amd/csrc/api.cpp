@@ -377,6 +377,99 @@ int sp_wave_step(const sp_grid *g, const sp_coeffs *c, double dt, double dx, con
     return ok();
 }
 
+int sp_wave_step_fused(const sp_grid *g, const sp_coeffs *c, double dt, double dx, const sp_grid *gv,
+                       const float *v, sp_wave_state *st, int nsteps, void **spare,
+                       const sp_sources *src, const sp_receivers *rec, void *stream) {
+    const char *who = "sp_wave_step_fused";
+    sp::SweepArgs a;
+    sp::TileCfg t;
+    if (int e = prep_wave(who, g, c, dt, dx, gv, v, src, rec, &a, &t)) return e;
+    if (g->dtype != SP_F32) return fail(SP_EUNSUPPORTED, "%s: FP32 grids only", who);
+    if (!st || !st->cur || !st->prev || st->meta) return fail(SP_EINVAL, "%s: bad state", who);
+    if (!spare || !spare[0] || !spare[1]) return fail(SP_EINVAL, "%s: NULL spare field", who);
+    if (nsteps < 0 || st->step < 0) return fail(SP_EINVAL, "%s: negative step count", who);
+    void *f[4] = {st->cur, st->prev, spare[0], spare[1]};
+    for (int i = 0; i < 4; ++i) {
+        if (!aligned16(f[i])) return fail(SP_EINVAL, "%s: pointers must be 16-byte aligned", who);
+        if (overlaps(f[i], v, g->bytes)) return fail(SP_EINVAL, "%s: v overlaps a wavefield", who);
+        for (int j = 0; j < i; ++j)
+            if (overlaps(f[i], f[j], g->bytes)) return fail(SP_EINVAL, "%s: wavefields overlap", who);
+    }
+
+    sp::TileCfg tb = sp::choose_tiles_tb2(g->nx, g->ny, g->nz);
+    // Optional override for tuning: SP_TILE_FUSED=RXxRR[xZC] (region extent)
+    if (const char *e = std::getenv("SP_TILE_FUSED")) {
+        int rx = 0, rr = 0, zc = 0;
+        const int n = std::sscanf(e, "%dx%dx%d", &rx, &rr, &zc);
+        if (n >= 2) {
+            tb.tx = rx;
+            tb.ty = rr;
+            tb.zchunk = sp::tb2_zchunk(tb, g->nx, g->ny, g->nz);
+        }
+        if (n == 3 && zc > 0) tb.zchunk = std::min(zc, g->nz);
+    }
+    if (!sp::tb2_supported(tb))
+        return fail(SP_EINVAL, "%s: region %dx%d is not compiled in", who, tb.tx, tb.ty);
+    sp::Tb2Args b;
+    std::memset(&b, 0, sizeof b);
+    b.v = a.v;
+    b.nx = g->nx;
+    b.ny = g->ny;
+    b.nz = g->nz;
+    b.sy = a.sy;
+    b.sz = a.sz;
+    b.vsy = a.vsy;
+    b.vsz = a.vsz;
+    b.m_scale = a.m_scale;
+    b.c = a.c;
+    b.src = a.src;
+    b.tiles_x = (g->nx + tb.tx - 9) / (tb.tx - 8);
+    b.tiles_y = (g->ny + tb.ty - 9) / (tb.ty - 8);
+    b.zchunk = tb.zchunk;
+    b.nzc = (g->nz + tb.zchunk - 1) / tb.zchunk;
+
+    const int nsrc = a.src.n;
+    const int nrec = rec ? rec->n : 0;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t step0 = st->step;
+    const int64_t org = g->origin;
+    auto at = [&](void *p) { return static_cast<float *>(p) + org; };
+    for (int k = 0; k + 1 < nsteps; k += 2) {
+        const int64_t n = st->step;
+        b.u = at(st->cur);
+        b.prev = at(st->prev);
+        b.out1 = at(spare[0]);
+        b.out2 = at(spare[1]);
+        if (nsrc) {
+            b.src.amp = src->amp + n * src->amp_stride;
+            b.amp1 = src->amp + (n + 1) * src->amp_stride;
+        }
+        hipError_t err = sp::launch_tb2(tb, b, s);
+        for (int h = 0; h < 2 && err == hipSuccess && nrec > 0; ++h)
+            err = sp::launch_record(SP_F32, h ? b.out2 : b.out1, nullptr, a.sy, a.sz, g->nx, g->ny,
+                                    g->nz, rec->xyz, nrec,
+                                    rec->traces + (n + h - step0) * rec->trace_stride, s);
+        if (err != hipSuccess)
+            return fail(SP_EDEVICE, "%s: launch failed at step %lld: %s", who, (long long)n,
+                        hipGetErrorString(err));
+        void *old_cur = st->cur, *old_prev = st->prev;
+        st->prev = spare[0];
+        st->cur = spare[1];
+        spare[0] = old_prev;
+        spare[1] = old_cur;
+        st->step += 2;
+    }
+    if (nsteps % 2) {
+        sp_receivers r1;
+        if (nrec > 0) {
+            r1 = *rec;
+            r1.traces = rec->traces + (st->step - step0) * rec->trace_stride;
+        }
+        return sp_wave_step(g, c, dt, dx, gv, v, st, 1, src, nrec > 0 ? &r1 : nullptr, stream);
+    }
+    return ok();
+}
+
 int sp_pml_profile(const sp_grid *gv, int width, double eta_max, float *eta, void *stream) {
     if (int e = check_grid(gv, "sp_pml_profile")) return e;
     if (gv->dtype != SP_F32) return fail(SP_EINVAL, "sp_pml_profile: eta must be an FP32 grid");

@@ -136,6 +136,28 @@ hipError_t launch_pack(const float *dense, float *field, int64_t sy, int64_t sz,
 hipError_t launch_unpack(int dtype, const void *field, const float *scale, float *dense,
                          int64_t sy, int64_t sz, int nx, int ny, int nz, hipStream_t s);
 
+// Two fused leapfrog steps (FP32): u^{n+1} into out1, u^{n+2} into out2.
+// Pointers at the interior origin; out1 and out2 distinct from u and prev.
+struct Tb2Args {
+    const float *u;      // u^n
+    const float *prev;   // u^{n-1}
+    const float *v;
+    float *out1, *out2;
+    int nx, ny, nz;
+    int64_t sy, sz;      // strides of u, prev, out1, out2
+    int64_t vsy, vsz;
+    float m_scale;       // (dt / dx)^2
+    StarCoef c;
+    SrcList src;         // amp: amplitudes of step n
+    const float *amp1;   // amplitudes of step n+1
+    int tiles_x, tiles_y, zchunk, nzc;
+};
+// tx x ty = region (inner tile plus a 4-point ring), zchunk planes per block.
+TileCfg choose_tiles_tb2(int nx, int ny, int nz);
+int tb2_zchunk(const TileCfg &t, int nx, int ny, int nz);
+bool tb2_supported(const TileCfg &t);
+hipError_t launch_tb2(const TileCfg &t, const Tb2Args &a, hipStream_t s);
+
 // Stencil suite (star/box, radius 1..4, 2D/3D, arbitrary weights; FP32).
 // u and out point at interior (0, 0, 0); a 2D kernel on a grid of several
 // planes treats each interior plane as its own 2D grid.

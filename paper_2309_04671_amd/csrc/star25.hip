@@ -33,12 +33,12 @@
 #include <type_traits>
 
 #include "internal.h"
+#include "kcommon.h"
 
 namespace sp {
 
 namespace {
 
-typedef float f4v __attribute__((ext_vector_type(4)));
 typedef _Float16 h4v __attribute__((ext_vector_type(4)));
 typedef uint16_t u4v __attribute__((ext_vector_type(4)));
 typedef __bf16 b4v __attribute__((ext_vector_type(4)));
@@ -99,26 +99,6 @@ template <> struct Io<__bf16> {
         return __builtin_elementwise_abs(__builtin_convertvector(r, f4v));
     }
 };
-
-__device__ __forceinline__ f4v ld4(const float *p) { return *reinterpret_cast<const f4v *>(p); }
-
-__device__ __forceinline__ f4v ld4_nt(const float *p) {
-    return __builtin_nontemporal_load(reinterpret_cast<const f4v *>(p));
-}
-
-// Barrier that orders LDS traffic only; pending global loads stay in flight.
-__device__ __forceinline__ void lds_barrier() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
-// Map a block index to a tile index so that each XCD receives one contiguous
-// range of tiles.  Bijective on [0, n) for any n.
-__device__ __forceinline__ int xcd_tile(int bid, int n) {
-    const int xcd = bid & 7, loc = bid >> 3, q = n >> 3, r = n & 7;
-    return xcd * q + (xcd < r ? xcd : r) + loc;
-}
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 

@@ -27,41 +27,11 @@
 #include <stdint.h>
 
 #include "internal.h"
+#include "kcommon.h"
 
 namespace sp {
 
 namespace {
-
-typedef float f4v __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ f4v ld4(const float *p) { return *reinterpret_cast<const f4v *>(p); }
-
-__device__ __forceinline__ void st4_nt(float *p, f4v v) {
-    __builtin_nontemporal_store(v, reinterpret_cast<f4v *>(p));
-}
-
-// Ragged row end: store the first n (1..4) values.
-__device__ __forceinline__ void st_part(float *p, f4v v, int n) {
-    if (n >= 4) {
-        st4_nt(p, v);
-    } else {
-        p[0] = v[0];
-        if (n > 1) p[1] = v[1];
-        if (n > 2) p[2] = v[2];
-    }
-}
-
-__device__ __forceinline__ void lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
-// Block index -> tile index, tiles contiguous per XCD (bijective on [0, n)).
-__device__ __forceinline__ int xcd_order(int bid, int n) {
-    const int xcd = bid & 7, loc = bid >> 3, q = n >> 3, r = n & 7;
-    return xcd * q + (xcd < r ? xcd : r) + loc;
-}
 
 // Element k (-4 <= k < 8) of the 12 values l | c | r around a lane's chunk.
 __device__ __forceinline__ float pick(const f4v &l, const f4v &c, const f4v &r, int k) {
@@ -92,7 +62,7 @@ __global__ __launch_bounds__(64 * WAVES2) void k_suite2(SuiteArgs a, Tile2 t,
     constexpr int D = 2 * R + 1;
     constexpr int QS = BOX ? D : 1;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    int lin = xcd_order(blockIdx.x, gridDim.x);
+    int lin = xcd_tile(blockIdx.x, gridDim.x);
     const int tx = lin % t.tiles_x;
     lin /= t.tiles_x;
     const int grp = lin % t.groups;
@@ -193,7 +163,7 @@ __global__ __launch_bounds__(64 * TY / RY) void k_suite3(SuiteArgs a, Tile3 t,
     __shared__ f4v lds[2][NCH];
 
     const int tid = threadIdx.x, lane = tid & 63, rg = tid >> 6;
-    int lin = xcd_order(blockIdx.x, gridDim.x);
+    int lin = xcd_tile(blockIdx.x, gridDim.x);
     const int tx = lin % t.tiles_x;
     lin /= t.tiles_x;
     const int ty = lin % t.tiles_y;
@@ -242,7 +212,7 @@ __global__ __launch_bounds__(64 * TY / RY) void k_suite3(SuiteArgs a, Tile3 t,
             const int c = tid + k * NT;
             if (k + 1 < K || c < NCH) L[c] = cur[k];
         }
-        lds_sync();
+        lds_barrier();
         // plane zp adds w[dz] * (its xy part) to output plane zp - dz, held
         // in acc[j][R - dz]
 #pragma unroll

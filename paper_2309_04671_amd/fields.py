@@ -85,10 +85,13 @@ class WaveState:
     bits]; field u^k uses slot k mod 4 (see include/stencil.h).
     """
 
-    def __init__(self, grid: lib.sp_grid, device="cuda"):
+    def __init__(self, grid: lib.sp_grid, device="cuda", spares: bool = False):
         self.grid = grid
         self.a = Field(grid, device)
         self.b = Field(grid, device)
+        # two more fields for sp_wave_step_fused (two steps per sweep)
+        self.extra = [Field(grid, device), Field(grid, device)] if spares else []
+        self.spare = [f.ptr for f in self.extra]
         nbytes = int(lib.load().sp_wave_meta_bytes(grid))
         self.meta = torch.zeros(max(nbytes // 4, 1), dtype=torch.float32, device=device)
         self.st = lib.sp_wave_state(self.b.ptr, self.a.ptr,
@@ -99,7 +102,10 @@ class WaveState:
         return nslab(self.grid.nz)
 
     def _by_ptr(self, p) -> Field:
-        return self.a if p == self.a.ptr else self.b
+        for f in [self.a, self.b] + self.extra:
+            if f.ptr == p:
+                return f
+        raise ValueError("pointer is not one of this state's fields")
 
     def cur(self) -> Field:
         return self._by_ptr(self.st.cur)
@@ -114,10 +120,11 @@ class WaveState:
         return self.meta[base:base + n], self.meta[base + n:base + 2 * n]
 
     def reset(self):
-        self.a.buf.zero_()
-        self.b.buf.zero_()
+        for f in [self.a, self.b] + self.extra:
+            f.buf.zero_()
         self.meta.zero_()
         self.st.cur, self.st.prev, self.st.step = self.b.ptr, self.a.ptr, 0
+        self.spare = [f.ptr for f in self.extra]
 
     def decoded(self, which="cur") -> np.ndarray:
         """Interior of u^n (or u^{n-1}) decoded to FP64 with its slab scales."""

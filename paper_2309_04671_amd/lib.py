@@ -25,7 +25,7 @@ ERROR_NAMES = {0: "SP_OK", 1: "SP_EINVAL", 2: "SP_EUNSUPPORTED", 3: "SP_EDEVICE"
 # Every symbol include/stencil.h declares (checked by the ABI tests).
 EXPORTS = [
     "sp_grid_init", "sp_grid_init_2d", "sp_stencil_apply", "sp_apply", "sp_wave_meta_bytes", "sp_wave_step",
-    "sp_wave_run_states", "sp_wave_adjoint_step", "sp_grad_finish", "sp_energy_ws_bytes",
+    "sp_wave_step_fused", "sp_wave_run_states", "sp_wave_adjoint_step", "sp_grad_finish", "sp_energy_ws_bytes",
     "sp_energy", "sp_pml_profile", "sp_wave_step_pml", "sp_shot_bytes", "sp_queue_create", "sp_submit", "sp_poll", "sp_queue_drain",
     "sp_queue_destroy", "sp_last_error", "sp_version",
 ]
@@ -124,6 +124,8 @@ def load():
     lib.sp_wave_meta_bytes.restype = i64
     lib.sp_wave_step.argtypes = [P(sp_grid), P(sp_coeffs), d, d, P(sp_grid), vp, P(sp_wave_state), i,
                                  P(sp_sources), P(sp_receivers), vp]
+    lib.sp_wave_step_fused.argtypes = [P(sp_grid), P(sp_coeffs), d, d, P(sp_grid), vp, P(sp_wave_state),
+                                       i, P(vp), P(sp_sources), P(sp_receivers), vp]
     lib.sp_wave_run_states.argtypes = [P(sp_grid), P(sp_coeffs), d, d, P(sp_grid), vp, P(vp), i64,
                                        i, P(sp_sources), P(sp_receivers), vp]
     lib.sp_wave_adjoint_step.argtypes = [P(sp_grid), P(sp_coeffs), d, d, P(sp_grid), vp,
@@ -266,6 +268,19 @@ def sp_wave_step(g, c, dt, dx, gv, v_ptr, state, nsteps, src=None, rec=None, str
 def _ptrs(ptrs):
     arr = (ctypes.c_void_p * len(ptrs))(*[int(p) for p in ptrs])
     return arr
+
+
+def sp_wave_step_fused(g, c, dt, dx, gv, v_ptr, state, nsteps, spare, src=None, rec=None,
+                       stream=None):
+    """Two leapfrog steps per sweep.  ``spare`` is a list of two device
+    pointers (zero-halo fields on g); like the state, it is rotated in place."""
+    arr = _ptrs(spare)
+    check(load().sp_wave_step_fused(ctypes.byref(g), ctypes.byref(c), float(dt), float(dx),
+                                    ctypes.byref(gv), ctypes.c_void_p(v_ptr), ctypes.byref(state),
+                                    int(nsteps), arr,
+                                    ctypes.byref(src) if src is not None else None,
+                                    ctypes.byref(rec) if rec is not None else None, stream_ptr(stream)))
+    spare[0], spare[1] = arr[0], arr[1]
 
 
 def sp_wave_run_states(g, c, dt, dx, gv, v_ptr, states, n0, nsteps, src=None, rec=None, stream=None):

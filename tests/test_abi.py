@@ -125,6 +125,34 @@ def test_wave_step_validates_before_launch():
     assert st.cur == 1 << 30 and st.step == 0
 
 
+def test_fused_step_validates_before_launch(monkeypatch):
+    L = lib.load()
+    g = lib.grid_init(32, 32, 32)
+    c = lib.coeffs({"center": -1, "ax": [0] * 4, "ay": [0] * 4, "az": [0] * 4})
+    big = g.bytes + 4096
+    cur, prev, s0, s1 = (1 << 30), (1 << 30) + big, (1 << 30) + 2 * big, (1 << 30) + 3 * big
+    st = lib.sp_wave_state(cur, prev, None, 0)
+    v = ctypes.c_void_p(1 << 40)
+
+    def call(spare, gg=g, n=2, state=st):
+        arr = (ctypes.c_void_p * 2)(*spare) if spare is not None else None
+        return L.sp_wave_step_fused(ctypes.byref(gg), ctypes.byref(c), 1e-3, 10.0, ctypes.byref(g),
+                                    v, ctypes.byref(state), n, arr, None, None, None)
+
+    assert call(None) == lib.SP_EINVAL
+    assert call([s0, None]) == lib.SP_EINVAL
+    assert call([s0, s0]) == lib.SP_EINVAL and "overlap" in lib.last_error()
+    assert call([s0, prev + 256]) == lib.SP_EINVAL and "overlap" in lib.last_error()
+    assert call([s0, s1 + 4]) == lib.SP_EINVAL and "aligned" in lib.last_error()
+    assert call([s0, (1 << 40) + 64]) == lib.SP_EINVAL        # overlaps v
+    assert call([s0, s1], n=-1) == lib.SP_EINVAL
+    g16 = lib.grid_init(32, 32, 32, dtype=lib.SP_F16)
+    assert call([s0, s1], gg=g16) in (lib.SP_EINVAL, lib.SP_EUNSUPPORTED)
+    monkeypatch.setenv("SP_TILE_FUSED", "64x40")
+    assert call([s0, s1]) == lib.SP_EINVAL and "not compiled" in lib.last_error()
+    assert st.cur == cur and st.prev == prev and st.step == 0
+
+
 def test_unknown_tile_override_is_rejected(monkeypatch):
     monkeypatch.setenv("SP_TILE", "96x7x1")
     L = lib.load()
