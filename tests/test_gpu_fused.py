@@ -137,6 +137,40 @@ def test_fused_bitwise_equal_to_single_step(gpu_lib, region, nsteps, monkeypatch
     assert set(wf.spare) == {f.ptr for f in [wf.a, wf.b] + wf.extra} - held
 
 
+@pytest.mark.parametrize("shape", [(1, 1, 1), (3, 2, 1), (5, 3, 2), (9, 70, 3), (57, 25, 9),
+                                   (200, 5, 70), (56, 40, 16), (112, 80, 33)])
+def test_fused_degenerate_and_exact_shapes_bitwise(gpu_lib, shape):
+    # Grids of one point, single planes and rows, fewer planes than the
+    # 4-plane start-up, and exact multiples of the 56 x 40 tile: six steps
+    # (three fused sweeps) equal six single steps bit for bit.
+    from paper_2309_04671_amd import fields
+    lib = _lib()
+    nx, ny, nz = shape
+    g, v, vf = _setup(nx, ny, nz, 7)
+    dx = 10.0
+    dt = synth.cfl_dt(v, dx)
+    co = synth.random_coeffs(nx + ny + nz)
+    src_xyz = np.array([[nx // 2, ny // 2, nz // 2], [nx - 1, 0, nz - 1]], np.int32)
+    amp = torch.tensor(np.linspace(-1e4, 2e4, 12).reshape(6, 2), dtype=torch.float32, device="cuda")
+    prev = synth.uniform_field((nz, ny, nx), 41)
+    cur = synth.uniform_field((nz, ny, nx), 42)
+    ws, wf = fields.WaveState(g), fields.WaveState(g, spares=True)
+    for w in (ws, wf):
+        w.a.set_interior(prev)
+        w.b.set_interior(cur)
+    src = lib.make_sources(src_xyz, amp.data_ptr(), 2)
+    lib.sp_wave_step(g, lib.coeffs(co), dt, dx, g, vf.ptr, ws.st, 6, src=src)
+    lib.sp_wave_step_fused(g, lib.coeffs(co), dt, dx, g, vf.ptr, wf.st, 6, wf.spare, src=src)
+    torch.cuda.synchronize()
+    assert np.array_equal(ws.cur().get_interior(), wf.cur().get_interior())
+    assert np.array_equal(ws.prev().get_interior(), wf.prev().get_interior())
+    # the halos of all four fields are still zero
+    for f in [wf.a, wf.b] + wf.extra:
+        pad = f.padded().cpu().numpy()
+        pad[4:-4, 4:-4, 4:-4] = 0
+        assert not pad.any()
+
+
 def test_fused_multi_step_with_receivers_vs_oracle(gpu_lib):
     from paper_2309_04671_amd import fields
     lib = _lib()
