@@ -1090,8 +1090,10 @@ TileCfg choose_tiles(int nx, int ny, int nz, int dtype, int mode) {
     //  * BF16 (about 107 VGPRs with one row per thread): 1024-thread
     //    256x16x1 tiles at four waves per SIMD (about 512 blocks) where the
     //    grid has at least two of them across x, else the FP16 choice;
-    //  * the FP32 APPLY sweep (8 B per point) runs best on 256x16x1 tiles
-    //    too, but with one long z-chunk per tile (about 256 blocks);
+    //  * the FP32 APPLY sweep (8 B per point) runs best on 128x32x2 tiles
+    //    with about 256 blocks (one long z-chunk per tile at 1024^2),
+    //    measured on live data: constant or overflowed fields run the same
+    //    kernel faster and had favoured other tiles;
     //  * the absorbing-layer mode runs one row per thread in 512-thread
     //    256x8x1 tiles, 64x16x1 or 32x32x1 for narrow boxes (the x slabs).
     // z-chunks are at least 16 planes (each chunk re-reads 8 planes of u,
@@ -1102,7 +1104,7 @@ TileCfg choose_tiles(int nx, int ny, int nz, int dtype, int mode) {
     static const Cand c32[3] = {{256, 16, 2, 256, 1}, {128, 16, 2, 512, 1}, {64, 16, 1, 512, 1}};
     static const Cand c16[3] = {{128, 16, 2, 4096, 1}, {128, 16, 2, 4096, 1}, {64, 16, 1, 4096, 1}};
     static const Cand cbf[3] = {{256, 16, 1, 512, 2}, {128, 16, 2, 4096, 1}, {64, 16, 1, 4096, 1}};
-    static const Cand cap[3] = {{256, 16, 1, 256, 2}, {128, 16, 2, 512, 1}, {64, 16, 1, 512, 1}};
+    static const Cand cap[3] = {{128, 32, 2, 256, 1}, {128, 16, 2, 512, 1}, {64, 16, 1, 512, 1}};
     static const Cand cpm[3] = {{256, 8, 1, 512, 1}, {64, 16, 1, 512, 1}, {32, 32, 1, 512, 1}};
     const Cand *cand = dtype == SP_F16    ? c16
                        : dtype == SP_BF16 ? cbf
