@@ -30,6 +30,8 @@ __device__ __forceinline__ void st_part(float *p, f4v v, int n) {
     }
 }
 
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
 // Barrier that orders LDS traffic only; pending global loads stay in flight.
 __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");

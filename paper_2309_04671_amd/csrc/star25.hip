@@ -100,8 +100,6 @@ template <> struct Io<__bf16> {
     }
 };
 
-__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
-
 // Depth of the halo-chunk register queue: the LDS frame of plane z is
 // fetched at iteration z-5, the iteration at which the tiles that own those
 // rows fetch them as their z-queue head, so the shared lines are read from

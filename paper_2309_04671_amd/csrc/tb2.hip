@@ -42,8 +42,6 @@ namespace sp {
 
 namespace {
 
-__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
-
 // Depth of the frame-chunk register queue (planes fetched ahead); measured
 // best of 1..5 on MI355X.
 constexpr int TB_HD = 3;
