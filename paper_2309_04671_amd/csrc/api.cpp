@@ -515,8 +515,6 @@ int sp_wave_step_pml(const sp_grid *g, const sp_coeffs *c, double dt, double dx,
     if (seven && (W < 4 || W % 4 != 0 || 2 * W >= nx || 2 * W >= ny || 2 * W >= nz))
         return fail(SP_EINVAL, "%s: the seven-region map needs W %% 4 == 0, W >= 4 and 2W < n (W = %d)",
                     who, W);
-    if (g->pitch_x * g->pitch_y >= ((int64_t)1 << 31))
-        return fail(SP_EUNSUPPORTED, "%s: planes of 2^31 or more elements", who);
 
     // Boxes [x0, x1) x [y0, y1) x [z0, z1), each swept by k_star25 on a
     // sub-grid whose pointers are offset to the box corner (its halo being
