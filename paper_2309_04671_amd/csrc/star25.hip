@@ -1094,7 +1094,8 @@ TileCfg choose_tiles(int nx, int ny, int nz, int dtype, int mode) {
     //    measured on live data: constant or overflowed fields run the same
     //    kernel faster and had favoured other tiles;
     //  * the absorbing-layer mode runs one row per thread in 512-thread
-    //    256x8x1 tiles, 64x16x1 or 32x32x1 for narrow boxes (the x slabs).
+    //    256x8x1 tiles, 64x16x1 or 32x32x1 for narrow boxes (the x slabs),
+    //    with the FP32 rule for the z-split;
     // z-chunks are at least 16 planes (each chunk re-reads 8 planes of u,
     // mostly from L2).  These targets are measured optima on MI355X.
     struct Cand {
@@ -1104,7 +1105,7 @@ TileCfg choose_tiles(int nx, int ny, int nz, int dtype, int mode) {
     static const Cand c16[3] = {{128, 16, 2, 4096, 1}, {128, 16, 2, 4096, 1}, {64, 16, 1, 4096, 1}};
     static const Cand cbf[3] = {{256, 16, 1, 512, 2}, {128, 16, 2, 4096, 1}, {64, 16, 1, 4096, 1}};
     static const Cand cap[3] = {{128, 32, 2, 256, 1}, {128, 16, 2, 512, 1}, {64, 16, 1, 512, 1}};
-    static const Cand cpm[3] = {{256, 8, 1, 512, 1}, {64, 16, 1, 512, 1}, {32, 32, 1, 512, 1}};
+    static const Cand cpm[3] = {{256, 8, 1, 256, 1}, {64, 16, 1, 512, 1}, {32, 32, 1, 512, 1}};
     const Cand *cand = dtype == SP_F16    ? c16
                        : dtype == SP_BF16 ? cbf
                        : mode == MODE_APPLY ? cap
@@ -1122,9 +1123,9 @@ TileCfg choose_tiles(int nx, int ny, int nz, int dtype, int mode) {
     }
     const int tiles = ((nx + t.tx - 1) / t.tx) * ((ny + t.ty - 1) / t.ty);
     int zc;
-    if (cand == c32) {
-        // FP32 leapfrog, gradient and energy sweeps: `want` blocks fill the
-        // GPU once.  Pick the z-split that maximises the filled share of the
+    if (cand == c32 || cand == cpm) {
+        // FP32 leapfrog, gradient, energy and layer sweeps: `want` blocks
+        // fill the GPU once (one 512-thread or two 256-thread blocks per CU).  Pick the z-split that maximises the filled share of the
         // last round times zc / (zc + 8) (each chunk also streams 8 planes
         // of start-up).  This keeps one chunk per tile when the tiles fill
         // whole rounds (1024^2 planes: 256 tiles) and avoids, for example,
