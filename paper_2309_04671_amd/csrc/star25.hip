@@ -1123,9 +1123,10 @@ TileCfg choose_tiles(int nx, int ny, int nz, int dtype, int mode) {
     }
     const int tiles = ((nx + t.tx - 1) / t.tx) * ((ny + t.ty - 1) / t.ty);
     int zc;
-    if (cand == c32 || cand == cpm) {
-        // FP32 leapfrog, gradient, energy and layer sweeps: `want` blocks
-        // fill the GPU once (one 512-thread or two 256-thread blocks per CU).  Pick the z-split that maximises the filled share of the
+    if (cand == c32 || cand == cpm || cand == cap) {
+        // FP32 sweeps (leapfrog, gradient, energy, layer, apply): `want`
+        // blocks fill the GPU once (one 512-thread or two 256-thread blocks
+        // per CU).  Pick the z-split that maximises the filled share of the
         // last round times zc / (zc + 8) (each chunk also streams 8 planes
         // of start-up).  This keeps one chunk per tile when the tiles fill
         // whole rounds (1024^2 planes: 256 tiles) and avoids, for example,
