@@ -5,6 +5,8 @@ Bars:
    in a mix of shapes and storage types, with graph replay or eager launches,
    and against a direct sp_wave_step run (same kernels, same arithmetic);
  * a queued FP32 shot matches the FP64 oracle (multi-step rel-L2 <= 1e-4);
+ * the four served shapes up to 384x384x256, FP32 and FP16 in one mix,
+   equal direct runs bit for bit;
  * requests submitted while others run are admitted before those finish.
 """
 
@@ -109,3 +111,34 @@ def test_late_requests_join_running_batch(gpu_lib):
         assert st.t_admit < st0.t_done          # admitted while the first still ran
         assert st.t_done < st0.t_done           # and finished before it
     cl.close()
+
+
+def test_c4_shapes_mixed_equal_direct_runs(gpu_lib):
+    # The four served grid shapes, FP32 and FP16 alternating, in one mix:
+    # every result equals a direct sp_wave_step run bit for bit, and the
+    # 128^3 FP32 shot matches the FP64 oracle.
+    from paper_2309_04671_amd import fields, lib, serve
+    specs = [(128, 128, 128, 0, 220), (192, 192, 160, 1, 240), (256, 256, 256, 0, 200),
+             (384, 384, 256, 1, 210)]
+    shots, res = _run(serve, lib, specs, slots=8, chunk=16)
+    for k, (p, s) in enumerate(shots):
+        nx, ny, nz, dtype, nsteps = specs[k]
+        g = lib.grid_init(nx, ny, nz, dtype)
+        gv = lib.grid_init(nx, ny, nz)
+        V = fields.Field(gv).set_interior(p["v"])
+        ws = fields.WaveState(g)
+        tr = torch.zeros_like(s.traces)
+        lib.sp_wave_step(g, lib.coeffs(synth.star25_coeffs()), p["dt"], p["dx"], gv, V.ptr, ws.st,
+                         nsteps, src=lib.make_sources(p["src"], s.amp.data_ptr(), 1),
+                         rec=lib.make_receivers(len(s.rec), s.rec_d.data_ptr(), tr.data_ptr(),
+                                                len(s.rec)))
+        torch.cuda.synchronize()
+        assert np.array_equal(tr.cpu().numpy(), res[k][0]), k
+        assert np.array_equal(ws.decoded().astype(np.float32), res[k][1]), k
+        del ws, V
+    p, s = shots[0]
+    ref = oracle.wave_run(synth.star25_coeffs(), p["v"], p["dt"], p["dx"], 220, src=p["src"],
+                          amp=s.amp.cpu().double().numpy(), rec=s.rec)
+    e = errors(res[0][1], oracle.interior(ref["cur"]))
+    print("served 128^3 FP32 shot vs oracle:", e)
+    assert e["rel_l2"] <= 1e-4
