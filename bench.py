@@ -314,10 +314,12 @@ def leg_adjoint(torch, lib, fields, synth, n=256, nt=1000, ckpt=32):
         return J, vv.grad
 
     # the first call also allocates the recompute ring and gradient buffers
+    torch.cuda.reset_peak_memory_stats()
     t0 = time.perf_counter()
     fwd_bwd()
     torch.cuda.synchronize()
     t_first = time.perf_counter() - t0
+    peak_gb = torch.cuda.max_memory_allocated() / 1e9
     t0 = time.perf_counter()
     J, g = fwd_bwd()
     torch.cuda.synchronize()
@@ -326,6 +328,7 @@ def leg_adjoint(torch, lib, fields, synth, n=256, nt=1000, ckpt=32):
     return {"config": "%d^3, %d steps, checkpoint every %d, %d receivers" % (n, nt, ckpt, len(rec)),
             "forward_s": round(t_fwd, 4), "forward_backward_s": round(t_all, 4),
             "first_call_s": round(t_first, 4),
+            "peak_memory_gb": round(peak_gb, 2),
             "ratio_vs_forward": round(t_all / t_fwd, 3),
             "effective_gbs": round(n ** 3 * nt * bytes_per_step / t_all / 1e9, 1),
             "misfit": float(J.detach()), "grad_finite": bool(torch.isfinite(g).all()),
@@ -464,10 +467,12 @@ def _serve_requests(torch, lib, serve, synth, n, seed0):
     return reqs
 
 
-def leg_serve(torch, lib, fields, synth, nreq=96, rho=0.8, budget_gb=200.0, slots=32, chunk=16):
+def leg_serve(torch, lib, fields, synth, nreq=96, loads=(0.5, 0.8, 1.0), budget_gb=200.0, slots=32,
+              chunk=16):
     """Served shot stream (continuous batching): capacity from a saturating
-    batch, then Poisson arrivals at offered load rho of that capacity;
-    latency = done - submit per request."""
+    batch, then a Poisson stream of nreq requests at each offered load (a
+    fraction of that capacity); latency = done - submit per request.  The
+    top-level figures are those at load 0.8; `loads` holds all three."""
     import numpy as np
     from paper_2309_04671_amd import serve
     budget = int(budget_gb * (1 << 30))
@@ -482,54 +487,70 @@ def leg_serve(torch, lib, fields, synth, nreq=96, rho=0.8, budget_gb=200.0, slot
     cap_s = time.perf_counter() - t0
     capacity = sum(s.points for s in sat) / cap_s / 1e9
     del sat
-    # Poisson stream at rho * capacity
-    reqs = _serve_requests(torch, lib, serve, synth, nreq, 0)
-    mean_pts = float(np.mean([s.points for s in reqs]))
-    rate = rho * capacity * 1e9 / mean_pts                 # requests per second
-    gaps = np.random.default_rng(7).exponential(1.0 / rate, nreq)
-    start = time.perf_counter()
-    t_arr = start + np.cumsum(gaps)
-    for s, ta in zip(reqs, t_arr):
-        d = ta - time.perf_counter()
-        if d > 0:
-            time.sleep(d)
-        cl.submit(s)
-    cl.drain()
-    lat, waits, done_t, sub_t = [], [], [], []
-    for s in reqs:
-        ok, st = cl.poll(s.ticket)
-        if not ok or st.state != lib.SP_SHOT_DONE:
-            raise RuntimeError("served shot failed: state %d error %d" % (st.state, st.error))
-        lat.append(st.t_done - st.t_submit)
-        waits.append(st.t_admit - st.t_submit)
-        done_t.append(st.t_done)
-        sub_t.append(st.t_submit)
-    makespan = max(done_t) - min(sub_t)
-    agg = sum(s.points for s in reqs) / makespan / 1e9
-    # two requests re-run alone must reproduce their traces bit for bit
-    solo_equal = True
-    small = sorted(range(nreq), key=lambda i: reqs[i].points)[:2]
-    for i in small:
-        s = reqs[i]
-        ref = s.traces.clone()
-        s.traces.zero_()
-        cl2 = serve.ServeClient(arena_bytes=4 << 30, max_slots=1, chunk_steps=chunk)
-        cl2.submit(s)
-        cl2.drain()
-        cl2.close()
-        solo_equal = solo_equal and bool(torch.equal(ref, s.traces))
-    cl.close()
-    lat = np.array(lat)
-    return {"config": "%d requests, Poisson arrivals at %.0f%% of capacity, shapes %s, steps U{200..2000}, "
-                      "FP32/FP16 50/50, budget %.0f GB, %d slots, %d-step chunks"
-                      % (nreq, rho * 100, SERVE_SHAPES, budget_gb, slots, chunk),
-            "capacity_gpts": round(capacity, 1),
-            "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
-            "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
-            "mean_admit_wait_s": round(float(np.mean(waits)), 4),
-            "aggregate_gpts": round(agg, 1), "makespan_s": round(makespan, 3),
-            "solo_equal_sampled": solo_equal}
 
+    def stream(rho, seed0):
+        reqs = _serve_requests(torch, lib, serve, synth, nreq, seed0)
+        mean_pts = float(np.mean([s.points for s in reqs]))
+        rate = rho * capacity * 1e9 / mean_pts                 # requests per second
+        gaps = np.random.default_rng(7 + seed0).exponential(1.0 / rate, nreq)
+        t_arr = time.perf_counter() + np.cumsum(gaps)
+        for s, ta in zip(reqs, t_arr):
+            d = ta - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            cl.submit(s)
+        cl.drain()
+        lat, waits, done_t, sub_t = [], [], [], []
+        for s in reqs:
+            ok, st = cl.poll(s.ticket)
+            if not ok or st.state != lib.SP_SHOT_DONE:
+                raise RuntimeError("served shot failed: state %d error %d" % (st.state, st.error))
+            lat.append(st.t_done - st.t_submit)
+            waits.append(st.t_admit - st.t_submit)
+            done_t.append(st.t_done)
+            sub_t.append(st.t_submit)
+        makespan = max(done_t) - min(sub_t)
+        lat = np.array(lat)
+        res = {"p50_latency_s": round(float(np.percentile(lat, 50)), 4),
+               "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
+               "mean_admit_wait_s": round(float(np.mean(waits)), 4),
+               "aggregate_gpts": round(sum(s.points for s in reqs) / makespan / 1e9, 1),
+               "makespan_s": round(makespan, 3)}
+        return res, reqs
+
+    per_load = {}
+    main_reqs = None
+    for k, rho in enumerate(loads):
+        res, reqs = stream(rho, 0 if abs(rho - 0.8) < 1e-9 else 1000 * (k + 1))
+        per_load["%.1f" % rho] = res
+        if abs(rho - 0.8) < 1e-9:
+            main_reqs = reqs
+        else:
+            del reqs
+    # two requests of the load-0.8 stream re-run alone must reproduce their
+    # traces bit for bit
+    solo_equal = True
+    if main_reqs is not None:
+        small = sorted(range(nreq), key=lambda i: main_reqs[i].points)[:2]
+        for i in small:
+            s = main_reqs[i]
+            ref = s.traces.clone()
+            s.traces.zero_()
+            cl2 = serve.ServeClient(arena_bytes=4 << 30, max_slots=1, chunk_steps=chunk)
+            cl2.submit(s)
+            cl2.drain()
+            cl2.close()
+            solo_equal = solo_equal and bool(torch.equal(ref, s.traces))
+    cl.close()
+    out = {"config": "%d requests per load, Poisson arrivals at %s of capacity, shapes %s, steps U{200..2000}, "
+                     "FP32/FP16 50/50, budget %.0f GB, %d slots, %d-step chunks"
+                     % (nreq, "/".join("%.0f%%" % (100 * r) for r in loads), SERVE_SHAPES, budget_gb, slots,
+                        chunk),
+           "capacity_gpts": round(capacity, 1)}
+    out.update(per_load.get("0.8", {}))
+    out["loads"] = per_load
+    out["solo_equal_sampled"] = solo_equal
+    return out
 
 
 def main():
