@@ -81,10 +81,24 @@ def cpu_baseline(min_seconds=10.0):
         prev, cur = r["prev"], r["cur"]
         steps += 2
     pts = nx * ny * nz * steps
-    return {"value": round(pts / elapsed / 1e9, 4), "unit": "GPts/s", "cores": oracle.num_threads(),
+    cores = oracle.num_threads()
+    # the same loop nest on one core: 2 steps of a 1024 x 1024 x 16 slab
+    n1 = 16
+    v1 = np.ascontiguousarray(v[:n1])
+    p1 = np.zeros((n1 + 8, ny + 8, nx + 8))
+    oracle.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.wave_run(co, v1, dt, dx, 2, prev=p1, cur=p1.copy())
+        t1 = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(cores)
+    return {"value": round(pts / elapsed / 1e9, 4), "unit": "GPts/s", "cores": cores,
             "kind": "oracle",
             "sample": "%dx%dx%d slab of the same layered model, %d FP64 leapfrog steps, %.1f s"
-                      % (nx, ny, nz, steps, elapsed)}
+                      % (nx, ny, nz, steps, elapsed),
+            "one_core_value": round(nx * ny * n1 * 2 / t1 / 1e9, 4),
+            "one_core_sample": "%dx%dx%d slab, 2 steps, %.2f s" % (nx, ny, n1, t1)}
 
 
 def leg_storage(torch, lib, fields, synth, steps=2, nt=1000, n=512):

@@ -57,6 +57,8 @@ def _load():
     lib.ref_wave_pml_run.restype = None
     lib.ref_num_threads.argtypes = []
     lib.ref_num_threads.restype = i
+    lib.ref_set_num_threads.argtypes = [i]
+    lib.ref_set_num_threads.restype = None
     _lib = lib
     return lib
 
@@ -89,6 +91,11 @@ def interior(p) -> np.ndarray:
 
 def num_threads() -> int:
     return _load().ref_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops (timing only)."""
+    _load().ref_set_num_threads(int(n))
 
 
 def laplacian(u_pad, coeffs) -> np.ndarray:

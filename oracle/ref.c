@@ -274,6 +274,18 @@ int ref_num_threads(void)
 #endif
 }
 
+/* Threads of the following parallel loops (timing only; results do not
+ * depend on it, each loop being over independent z-planes). */
+void ref_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}
+
 /*
  * Stencil suite of the paper's accuracy study (Sec. 6, the star/box kernels
  * of radius 1..4 in 2D and 3D; Eq. 3's 25-point star is star3d4r with
