@@ -277,3 +277,41 @@ def test_every_tile_config_single_step(gpu_lib, tile, monkeypatch):
     torch.cuda.synchronize()
     e = errors(W.get_interior(), oracle.laplacian(oracle.padded(cur), co))
     assert e["rel_l2"] <= TOL_SWEEP, (tile, e)
+
+
+SHAPES_DEFAULT = [(1, 1, 1), (5, 1, 3), (300, 300, 1), (17, 260, 9), (700, 33, 18), (129, 129, 129),
+                  (520, 260, 50), (96, 384, 31), (1000, 8, 40), (257, 255, 67)]
+
+
+@pytest.mark.parametrize("shape", SHAPES_DEFAULT)
+def test_default_launch_on_many_shapes(gpu_lib, shape):
+    # The default tile and z-split choice (which depends on the shape) on
+    # shapes from one point to several rounds of blocks: two leapfrog steps
+    # from a random state with a source, and one apply sweep, against the
+    # oracle.
+    from paper_2309_04671_amd import fields
+    lib = _lib()
+    nx, ny, nz = shape
+    g, v, vf = _wave_setup(nx, ny, nz, 9)
+    dx = 10.0
+    dt = synth.cfl_dt(v, dx)
+    co = synth.random_coeffs(nx + 2 * ny + 3 * nz)
+    prev = synth.uniform_field((nz, ny, nx), 51)
+    cur = synth.uniform_field((nz, ny, nx), 52)
+    P = fields.Field(g).set_interior(prev)
+    C = fields.Field(g).set_interior(cur)
+    src_xyz = np.array([[nx // 3, ny // 2, nz - 1]], np.int32)
+    amp = torch.tensor([[2.0e3], [-1.0e3]], dtype=torch.float32, device="cuda")
+    st = lib.sp_wave_state(C.ptr, P.ptr, None, 0)
+    lib.sp_wave_step(g, lib.coeffs(co), dt, dx, g, vf.ptr, st, 2,
+                     src=lib.make_sources(src_xyz, amp.data_ptr(), 1))
+    torch.cuda.synchronize()
+    r = oracle.wave_run(co, v, dt, dx, 2, src=src_xyz, amp=amp.cpu().double().numpy(),
+                        prev=oracle.padded(prev), cur=oracle.padded(cur))
+    got = fields.Field(g, buf=C.buf if st.cur == C.ptr else P.buf).get_interior()
+    e = errors(got, oracle.interior(r["cur"]))
+    assert e["rel_l2"] <= TOL_SWEEP, (shape, e)
+    u, out, where = _apply(prev, co, 1)
+    assert where == 1
+    e = errors(out.get_interior(), oracle.laplacian(oracle.padded(prev), co))
+    assert e["rel_l2"] <= TOL_SWEEP, (shape, e)
