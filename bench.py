@@ -401,8 +401,9 @@ def leg_fused(torch, lib, fields, synth, nt=100):
 def leg_pml(torch, lib, fields, synth, nt=100, width=32):
     """Leapfrog with the absorbing layer on the 1024x1024x512 workload (layer
     of `width` cells on every face): the seven-region map (inner box by the
-    streaming kernel, six slabs by the layer kernel), the unified map (layer
-    kernel everywhere) and the plain leapfrog, nt steps each after a
+    streaming kernel, six slabs by the layer kernel), the two-region map
+    (the six slabs in one launch), the unified map (layer kernel everywhere)
+    and the plain leapfrog, nt steps each after a
     warm-up run; the layer kernel's own rate at its 28 B per point."""
     import numpy as np
     nx, ny, nz = NX, NY, NZ
@@ -425,6 +426,9 @@ def leg_pml(torch, lib, fields, synth, nt=100, width=32):
             "seven_region": lambda: lib.sp_wave_step_pml(g, co, dt, dx, g, V.ptr, ws.st, nt,
                                                          lib.make_pml(width, E.ptr, PSI.ptr, alpha, 1),
                                                          src=src, stream=stream),
+            "two_region": lambda: lib.sp_wave_step_pml(g, co, dt, dx, g, V.ptr, ws.st, nt,
+                                                       lib.make_pml(width, E.ptr, PSI.ptr, alpha, 2),
+                                                       src=src, stream=stream),
             "unified": lambda: lib.sp_wave_step_pml(g, co, dt, dx, g, V.ptr, ws.st, nt,
                                                     lib.make_pml(width, E.ptr, PSI.ptr, alpha, 0),
                                                     src=src, stream=stream)}

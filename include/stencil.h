@@ -308,13 +308,15 @@ int sp_energy(const sp_grid *g, const sp_coeffs *c, double dt, double dx,
 
 #define SP_PML_UNIFIED 0   /* the layer kernel over the whole interior */
 #define SP_PML_SEVEN   1   /* inner box by the leapfrog kernel, 6 slabs by the layer kernel */
+#define SP_PML_TWO     2   /* inner box by the leapfrog kernel, the shell by one layer launch */
 
 typedef struct {
-    int32_t width;          /* W: layer cells on every face (SEVEN: W % 4 == 0, 4 <= W, 2W < n) */
-    int32_t decomposition;  /* SP_PML_UNIFIED or SP_PML_SEVEN (the paper's region maps) */
+    int32_t width;          /* W: layer cells on every face (SEVEN, TWO: W % 4 == 0, 4 <= W, 2W < n) */
+    int32_t decomposition;  /* SP_PML_UNIFIED, SP_PML_SEVEN or SP_PML_TWO (the paper's
+                               region maps: one region, seven boxes, inner box + shell) */
     double alpha;           /* frequency shift of the auxiliary equation (1/s), >= 0 */
     const float *eta;       /* DEVICE FP32 field on gv's layout, frame included: damping (1/s).
-                               SEVEN requires eta = 0 on the inner box [W, n-W) and on the
+                               SEVEN and TWO require eta = 0 on the inner box [W, n-W) and on the
                                cells next to it, as sp_pml_profile makes it */
     float *psi;             /* DEVICE FP32 field on g's layout: psi, zero before the first step */
 } sp_pml;

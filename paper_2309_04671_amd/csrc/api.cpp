@@ -509,11 +509,12 @@ int sp_wave_step_pml(const sp_grid *g, const sp_coeffs *c, double dt, double dx,
     if (!(pml->alpha >= 0) || !std::isfinite(pml->alpha))
         return fail(SP_EINVAL, "%s: alpha must be finite and >= 0", who);
     const int W = pml->width, nx = g->nx, ny = g->ny, nz = g->nz;
-    const bool seven = pml->decomposition == SP_PML_SEVEN;
-    if (!seven && pml->decomposition != SP_PML_UNIFIED)
-        return fail(SP_EINVAL, "%s: unknown decomposition %d", who, pml->decomposition);
+    const int dec = pml->decomposition;
+    if (dec != SP_PML_UNIFIED && dec != SP_PML_SEVEN && dec != SP_PML_TWO)
+        return fail(SP_EINVAL, "%s: unknown decomposition %d", who, dec);
+    const bool seven = dec != SP_PML_UNIFIED;   // SEVEN and TWO share the box layout
     if (seven && (W < 4 || W % 4 != 0 || 2 * W >= nx || 2 * W >= ny || 2 * W >= nz))
-        return fail(SP_EINVAL, "%s: the seven-region map needs W %% 4 == 0, W >= 4 and 2W < n (W = %d)",
+        return fail(SP_EINVAL, "%s: the region maps need W %% 4 == 0, W >= 4 and 2W < n (W = %d)",
                     who, W);
 
     // Boxes [x0, x1) x [y0, y1) x [z0, z1), each swept by k_star25 on a
@@ -549,6 +550,15 @@ int sp_wave_step_pml(const sp_grid *g, const sp_coeffs *c, double dt, double dx,
             b.a.src.z[q] -= z0;
         }
         b.t = sp::choose_tiles(b.a.nx, b.a.ny, b.a.nz, SP_F32, mode);
+        if (dec == SP_PML_TWO && mode == sp::MODE_PML) {
+            // the shell as one launch: every slab on 32x32x1 tiles, 512
+            // blocks of 256 threads per round
+            b.t.tx = 32;
+            b.t.ty = 32;
+            b.t.ry = 1;
+            b.t.zchunk = sp::occupancy_zchunk((int64_t)((b.a.nx + 31) / 32) * ((b.a.ny + 31) / 32),
+                                              b.a.nz, 512);
+        }
         fill_tiling(b.a, b.t);
     };
     if (!seven) {
@@ -572,13 +582,28 @@ int sp_wave_step_pml(const sp_grid *g, const sp_coeffs *c, double dt, double dx,
         float *prev = static_cast<float *>(st->prev) + g->origin;
         const float *amp = a.src.n ? src->amp + n * src->amp_stride : nullptr;
         hipError_t err = hipSuccess;
-        for (int q = 0; q < nb && err == hipSuccess; ++q) {
+        for (int q = 0; q < nb; ++q) {
             Box &b = boxes[q];
             b.a.u = cur + b.off;
             b.a.prev = prev + b.off;
             b.a.out = prev + b.off;
             b.a.src.amp = amp;
-            err = sp::launch_sweep(b.mode, SP_F32, b.t, b.a, s);
+        }
+        if (dec == SP_PML_TWO) {
+            // inner box, then the six slabs of the shell in one launch
+            err = sp::launch_sweep(boxes[0].mode, SP_F32, boxes[0].t, boxes[0].a, s);
+            sp::BoxSet shell;
+            shell.n = nb - 1;
+            shell.first[0] = 0;
+            for (int q = 1; q < nb; ++q) {
+                const sp::SweepArgs &ba = boxes[q].a;
+                shell.a[q - 1] = ba;
+                shell.first[q] = shell.first[q - 1] + ba.tiles_x * ba.tiles_y * ba.nzc;
+            }
+            if (err == hipSuccess) err = sp::launch_sweep_boxes(sp::MODE_PML, boxes[1].t, shell, s);
+        } else {
+            for (int q = 0; q < nb && err == hipSuccess; ++q)
+                err = sp::launch_sweep(boxes[q].mode, SP_F32, boxes[q].t, boxes[q].a, s);
         }
         if (err == hipSuccess && nrec > 0)
             err = sp::launch_record(SP_F32, prev, nullptr, a.sy, a.sz, nx, ny, nz, rec->xyz, nrec,

@@ -903,6 +903,19 @@ k_star25(SweepArgs a) {
     star25_body<TX, TY, RY, MODE, T>(a, xcd_tile(blockIdx.x, gridDim.x));
 }
 
+// Several boxes of one grid in one launch (the absorbing layer's shell as
+// one region): block b sweeps tile b - first[k] of box k, the box whose
+// block range holds b; each XCD receives one contiguous range of blocks.
+template <int TX, int TY, int RY, int MODE, typename T>
+__global__ void __launch_bounds__((TX / 4) * (TY / RY)) k_star25_boxes(const BoxSet bs) {
+    const int lin = xcd_tile(blockIdx.x, gridDim.x);
+    int k = 0;
+#pragma unroll
+    for (int i = 1; i < MAX_BOXES; ++i)
+        if (i < bs.n && lin >= bs.first[i]) k = i;
+    star25_body<TX, TY, RY, MODE, T>(bs.a[k], lin - bs.first[k]);
+}
+
 // Batched form: block b computes tile table[b].y of grid table[b].x, whose
 // arguments are args[table[b].x].  The host lays the table out so that each
 // XCD receives contiguous tiles of the same grid.
@@ -1075,6 +1088,28 @@ bool tile_supported(const TileCfg &t) {
            (t.tx == 256 && t.ty == 8 && t.ry == 1);
 }
 
+int occupancy_zchunk(int64_t tiles, int nz, int per_round) {
+    // Pick the z-split that maximises the filled share of the last round of
+    // per_round blocks times zc / (zc + 8) (each chunk also streams 8
+    // planes of start-up).  This keeps one chunk per tile when the tiles
+    // fill whole rounds (1024^2 planes: 256 tiles) and avoids, for example,
+    // 288 blocks on a 768^2 plane (1.125 rounds: 64-plane chunks run 30 %
+    // faster there, measured).
+    int best_k = 1;
+    double best = -1.0;
+    for (int k = 1; k <= 64; ++k) {
+        const int z = (nz + k - 1) / k;
+        if (k > 1 && z < 16) break;
+        const double rounds = (double)tiles * ((nz + z - 1) / z) / per_round;
+        const double eff = rounds / std::ceil(rounds) * z / (z + 8.0);
+        if (eff > best + 1e-9) {
+            best = eff;
+            best_k = k;
+        }
+    }
+    return (nz + best_k - 1) / best_k;
+}
+
 TileCfg choose_tiles(int nx, int ny, int nz, int dtype, int mode) {
     // Widest tile that does not waste more than a quarter of its columns on
     // the ragged x edge: wide tiles keep the x-halo (one 128-byte line per
@@ -1126,25 +1161,8 @@ TileCfg choose_tiles(int nx, int ny, int nz, int dtype, int mode) {
     if (cand == c32 || cand == cpm || cand == cap) {
         // FP32 sweeps (leapfrog, gradient, energy, layer, apply): `want`
         // blocks fill the GPU once (one 512-thread or two 256-thread blocks
-        // per CU).  Pick the z-split that maximises the filled share of the
-        // last round times zc / (zc + 8) (each chunk also streams 8 planes
-        // of start-up).  This keeps one chunk per tile when the tiles fill
-        // whole rounds (1024^2 planes: 256 tiles) and avoids, for example,
-        // 288 blocks on a 768^2 plane (1.125 rounds: 64-plane chunks run
-        // 30 % faster there, measured).
-        int best_k = 1;
-        double best = -1.0;
-        for (int k = 1; k <= 64; ++k) {
-            const int z = (nz + k - 1) / k;
-            if (k > 1 && z < 16) break;
-            const double rounds = (double)tiles * ((nz + z - 1) / z) / want;
-            const double eff = rounds / std::ceil(rounds) * z / (z + 8.0);
-            if (eff > best + 1e-9) {
-                best = eff;
-                best_k = k;
-            }
-        }
-        zc = (nz + best_k - 1) / best_k;
+        // per CU).
+        zc = occupancy_zchunk(tiles, nz, want);
     } else {
         const int chunks = (want + tiles - 1) / tiles;
         zc = (nz + chunks - 1) / chunks;
@@ -1153,6 +1171,15 @@ TileCfg choose_tiles(int nx, int ny, int nz, int dtype, int mode) {
     if (zc > nz) zc = nz;
     t.zchunk = zc < 1 ? 1 : zc;
     return t;
+}
+
+hipError_t launch_sweep_boxes(int mode, const TileCfg &t, const BoxSet &bs, hipStream_t s) {
+    // the layer mode on 32x32x1 tiles, the tile of the narrowest slabs
+    if (mode != MODE_PML || t.tx != 32 || t.ty != 32 || t.ry != 1 || bs.n < 1 || bs.n > MAX_BOXES)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_star25_boxes<32, 32, 1, MODE_PML, float>), dim3(bs.first[bs.n]), dim3(256), 0, s,
+                       bs);
+    return hipGetLastError();
 }
 
 bool batch_supported(const TileCfg &t) {

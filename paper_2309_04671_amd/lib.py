@@ -65,7 +65,7 @@ class sp_pml(ctypes.Structure):
                 ("alpha", ctypes.c_double), ("eta", ctypes.c_void_p), ("psi", ctypes.c_void_p)]
 
 
-SP_PML_UNIFIED, SP_PML_SEVEN = 0, 1
+SP_PML_UNIFIED, SP_PML_SEVEN, SP_PML_TWO = 0, 1, 2
 
 
 class sp_wave_state(ctypes.Structure):

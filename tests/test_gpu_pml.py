@@ -50,7 +50,7 @@ def test_profile_kernel_matches_the_profile(gpu_lib):
         assert np.all(np.abs(got - ref) <= 1e-6 * np.abs(ref))
 
 
-@pytest.mark.parametrize("decomp", [0, 1])
+@pytest.mark.parametrize("decomp", [0, 1, 2])
 def test_single_step_parity(gpu_lib, decomp):
     from paper_2309_04671_amd import fields, lib
     nx, ny, nz, W = 70, 45, 52, 8
@@ -101,19 +101,22 @@ def _multi(decomp, nx, ny, nz, W, steps):
 
 
 @pytest.mark.parametrize("shape", [(70, 45, 52, 8), (41, 33, 29, 4), (96, 64, 80, 12)])
-def test_multi_step_both_maps_match_the_oracle(gpu_lib, shape):
+def test_multi_step_all_maps_match_the_oracle(gpu_lib, shape):
     nx, ny, nz, W = shape
     steps = 80
     (v, eta, dx, dt, src, amp, rec), u7, p7, t7 = _multi(1, nx, ny, nz, W, steps)
     _, u1, p1, t1 = _multi(0, nx, ny, nz, W, steps)
+    _, u2, p2, t2 = _multi(2, nx, ny, nz, W, steps)
     r = oracle.wave_pml_run(synth.star25_coeffs(), v, eta, dt, dx, steps, src=src, amp=amp, rec=rec,
                             alpha=ALPHA)
     ref_u, ref_p = oracle.interior(r["cur"]), oracle.interior(r["psi"])
-    for u, p, t in ((u7, p7, t7), (u1, p1, t1)):
+    for u, p, t in ((u7, p7, t7), (u1, p1, t1), (u2, p2, t2)):
         assert errors(u, ref_u)["rel_l2"] <= 1e-4
         assert errors(p, ref_p)["rel_l2"] <= 1e-4
         assert errors(t, r["traces"])["rel_l2"] <= 1e-4
     assert errors(u7, u1)["rel_l2"] <= 1e-5 and errors(t7, t1)["rel_l2"] <= 1e-5
+    # the two-region map runs the same per-point arithmetic as the seven-region map
+    assert np.array_equal(u2, u7) and np.array_equal(p2, p7) and np.array_equal(t2, t7)
 
 
 def test_layer_absorbs_on_the_gpu(gpu_lib):
@@ -142,7 +145,7 @@ def test_validation(gpu_lib):
     F = [fields.Field(g) for _ in range(5)]
     st = lib.sp_wave_state(F[0].ptr, F[1].ptr, None, 0)
     co = lib.coeffs(synth.star25_coeffs())
-    for W, d, alpha in ((6, 1, 0.0), (20, 1, 0.0), (8, 5, 0.0), (8, 1, -1.0)):
+    for W, d, alpha in ((6, 1, 0.0), (20, 1, 0.0), (8, 5, 0.0), (8, 1, -1.0), (6, 2, 0.0), (20, 2, 0.0)):
         with pytest.raises(lib.SpError):
             lib.sp_wave_step_pml(g, co, 1e-3, 10.0, g, F[2].ptr, st, 1,
                                  lib.make_pml(W, F[3].ptr, F[4].ptr, alpha, d))
@@ -150,9 +153,10 @@ def test_validation(gpu_lib):
         lib.sp_wave_step_pml(g, co, 1e-3, 10.0, g, F[2].ptr, st, 1, lib.make_pml(8, F[3].ptr, F[1].ptr))
 
 
-def test_bench_size_sampled(gpu_lib):
-    # 512^3 with a 32-cell layer, seven-region map, one step from a random
-    # state: sampled points (layer and inner) against oracle windows
+@pytest.mark.parametrize("decomp", [1, 2])
+def test_bench_size_sampled(gpu_lib, decomp):
+    # 512^3 with a 32-cell layer, seven- and two-region maps, one step from a
+    # random state: sampled points (layer and inner) against oracle windows
     from paper_2309_04671_amd import fields, lib
     n, W = 512, 32
     g, v, V, dx, dt, eta, E, PSI = _setup(n, n, n, W, 0)
@@ -165,7 +169,7 @@ def test_bench_size_sampled(gpu_lib):
     before = {k: f.padded().clone() for k, f in (("p", P), ("c", C), ("s", PSI))}
     st = lib.sp_wave_state(C.ptr, P.ptr, None, 0)
     lib.sp_wave_step_pml(g, lib.coeffs(synth.star25_coeffs()), dt, dx, g, V.ptr, st, 1,
-                         lib.make_pml(W, E.ptr, PSI.ptr, ALPHA, 1))
+                         lib.make_pml(W, E.ptr, PSI.ptr, ALPHA, decomp))
     torch.cuda.synchronize()
     out_u, out_p = P.padded(), PSI.padded()
     Vp = V.padded()
