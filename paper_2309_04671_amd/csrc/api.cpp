@@ -484,6 +484,9 @@ int sp_pml_profile(const sp_grid *gv, int width, double eta_max, float *eta, voi
     return ok();
 }
 
+// The shell's slabs reach the multi-box kernel as one by-value argument.
+static_assert(sizeof(sp::BoxSet) <= 4096, "BoxSet exceeds the 4 KB kernel-argument limit");
+
 int sp_wave_step_pml(const sp_grid *g, const sp_coeffs *c, double dt, double dx, const sp_grid *gv,
                      const float *v, sp_wave_state *st, int nsteps, const sp_pml *pml,
                      const sp_sources *src, const sp_receivers *rec, void *stream) {
