@@ -40,7 +40,7 @@ extern "C" {
 /* status codes */
 #define SP_OK           0
 #define SP_EINVAL       1  /* bad argument (shape, halo, pointer, alignment, aliasing) */
-#define SP_EUNSUPPORTED 2  /* valid request this build does not implement */
+#define SP_EUNSUPPORTED 2  /* valid request the library does not implement */
 #define SP_EDEVICE      3  /* HIP runtime error */
 #define SP_ENOMEM       4  /* caller workspace / arena too small */
 #define SP_EBUDGET      5  /* shot can never fit the queue's HBM budget */
