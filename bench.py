@@ -148,12 +148,13 @@ SUITE_FLOPS = {"j2d5pt": 10, "j2d9pt-gol": 18, "j2d9pt": 18, "j3d27pt": 54}
 VALU_PEAK_GFLOPS = 78600.0      # FP32 FMA on all 256 CUs without packed-FP32 forms
 
 
-def leg_suite(torch, lib, fields, synth, sweeps=10):
+def leg_suite(torch, lib, fields, synth, sweeps=10, apply_only=False):
     """Stencil suite throughput: the 25-point sp_stencil_apply at 512^3 and
     1024x1024x512, and every suite kernel through sp_apply (3D: 512^3; 2D:
     one 8192^2 plane), `sweeps` ping-pong sweeps each; GPts/s, GB/s at 8 B
     per point, GFLOP/s, and the fraction of the binding peak (HBM 8 TB/s or
-    the 78.6 TFLOP/s FP32 VALU)."""
+    the 78.6 TFLOP/s FP32 VALU).  apply_only: the 25-point apply alone (a
+    short run for counter collection)."""
     import numpy as np
     stream = torch.cuda.current_stream()
     out = {}
@@ -215,6 +216,10 @@ def leg_suite(torch, lib, fields, synth, sweeps=10):
         g = lib.grid_init(*n3)
         ms, ok = timed(g, lambda g, a, b, k: lib.sp_stencil_apply(g, co, k, a.ptr, b.ptr, stream=stream))
         record("apply25_%dx%dx%d" % n3, g, ms, 49, ok)
+    if apply_only:
+        out["config"] = ("median of 3 batches of %d sweeps each after about 150 ms of warm-up sweeps; "
+                         "inputs U[0,1) FP32; the FD8 weights over sum |c|" % sweeps)
+        return out
     # NEXT-2 A/B on equal terms: the accumulating z-stream (sp_apply,
     # star3d4r) with the very weights and input of the register-queue
     # apply25 at 512^3 above, so both sweep the same data.
@@ -727,6 +732,9 @@ def main():
     if "suite" in legs:
         log("stencil suite")
         forms["suite"] = leg_suite(torch, lib, fields, synth)
+    elif "apply" in legs:                  # the 25-point apply alone (counter runs)
+        log("25-point apply")
+        forms["apply"] = leg_suite(torch, lib, fields, synth, apply_only=True)
     if "serve" in legs:
         log("served shot stream")
         torch.cuda.empty_cache()
