@@ -28,6 +28,16 @@ double now_s() {
 
 int64_t align256(int64_t b) { return (b + 255) / 256 * 256; }
 
+// Planes per block of a shot that shares its launch with other shots.  A
+// lone grid is split along z only as far as it needs to fill the GPU; in a
+// batch the other shots supply that parallelism, and short, equal chunks
+// keep the launch's tail short.  Measured on a saturating batch of the four
+// served shapes: 16 beats the lone-grid split by 1.8 % in capacity, 8 and 12
+// lose to the re-read start-up planes, 24 and longer to the tail.  A shot
+// alone in its launch keeps its own split.  The z-split never changes a
+// point's arithmetic.
+constexpr int QUEUE_ZCHUNK = 16;
+
 // Same block -> tile map as the single-grid kernels (contiguous per XCD).
 int xcd_tile_host(int bid, int n) {
     const int xcd = bid & 7, loc = bid >> 3, q = n >> 3, r = n & 7;
@@ -82,8 +92,10 @@ struct Shot {
     sp_shot_desc d;
     sp_grid g, gv;
     sp::TileCfg tile;
-    sp::SweepArgs base;          // validated arguments without per-step fields
-    int nblk = 0;
+    sp::SweepArgs base;          // validated arguments without per-step fields (own z-split)
+    int nblk = 0;                // blocks at the batch z-split (at least those of base)
+    sp::SweepArgs run;           // base with the z-split of the current composition
+    int nblk_run = 0;
     int64_t bytes = 0, off = -1;
     int64_t step = 0;
     int state = SP_SHOT_QUEUED, error = 0;
@@ -187,8 +199,17 @@ int rebuild(sp_queue *q, const std::vector<Shot *> &act, int k) {
             gp->tile = s.tile;
         }
         gp->members.push_back(&s);
-        gp->nblk += s.nblk;
         gp->nrec += std::max(0, s.d.nrec);
+    }
+    for (auto &g : q->groups) {
+        for (Shot *m : g.members) {
+            const int zc = g.members.size() > 1 ? std::min(m->base.zchunk, QUEUE_ZCHUNK) : m->base.zchunk;
+            m->run = m->base;
+            m->run.zchunk = zc;
+            m->run.nzc = (m->g.nz + zc - 1) / zc;
+            m->nblk_run = m->run.tiles_x * m->run.tiles_y * m->run.nzc;
+            g.nblk += m->nblk_run;
+        }
     }
     // static part: tables and receiver maps; dynamic part: per-step arguments
     int64_t off = 0;
@@ -216,7 +237,7 @@ int rebuild(sp_queue *q, const std::vector<Shot *> &act, int k) {
     for (auto &g : q->groups) {
         int2 *table = reinterpret_cast<int2 *>(q->pinned + g.off_table);
         std::vector<int> prefix(1, 0);
-        for (Shot *m : g.members) prefix.push_back(prefix.back() + m->nblk);
+        for (Shot *m : g.members) prefix.push_back(prefix.back() + m->nblk_run);
         for (int b = 0; b < g.nblk; ++b) {
             const int gl = xcd_tile_host(b, g.nblk);
             const int m = int(std::upper_bound(prefix.begin(), prefix.end(), gl) - prefix.begin()) - 1;
@@ -269,7 +290,7 @@ int run_chunk(sp_queue *q, int k) {
             for (int i = 0; i < k; ++i) {
                 const int64_t n = s.step + i;
                 sp::SweepArgs &a = args[(int64_t)i * nm + m];
-                a = s.base;
+                a = s.run;
                 a.v = s.v + s.gv.origin;
                 sp::step_args(a, &s.g, cur, prev, prev, s.meta, n, s.d.src_amp, s.d.nsrc);
                 sp::RecArgs &r = recs[(int64_t)i * nm + m];
@@ -513,7 +534,8 @@ int sp_submit(sp_queue *q, const sp_shot_desc *d, uint64_t *ticket) {
                               reinterpret_cast<const float *>(q->cfg.arena), d->nsrc ? &src : nullptr,
                               d->nrec ? &rec : nullptr, &s.base, &s.tile))
         return e;
-    s.nblk = s.base.tiles_x * s.base.tiles_y * s.base.nzc;
+    s.nblk = s.base.tiles_x * s.base.tiles_y * ((s.g.nz + std::min(s.base.zchunk, QUEUE_ZCHUNK) - 1) /
+                                                std::min(s.base.zchunk, QUEUE_ZCHUNK));
     if (!sp::batch_supported(s.tile))
         return fail(SP_EUNSUPPORTED, "sp_submit: tile configuration %dx%dx%d is not batched",
                     s.tile.tx, s.tile.ty, s.tile.ry);
