@@ -1117,7 +1117,8 @@ TileCfg choose_tiles(int nx, int ny, int nz, int dtype, int mode) {
     // rows per thread share their y-neighbour reads.  The candidates depend
     // on the storage type, because what limits each kernel differs:
     //  * FP32 (184 VGPRs, 16-byte accesses): 512-thread 256x16x2 tiles, one
-    //    block per CU, z split only when there are fewer than 256 tiles;
+    //    block per CU, z split only when there are fewer than 256 tiles
+    //    (the leapfrog on grids that need 16-plane chunks: 256x16x1);
     //  * FP16 (about 150 VGPRs, 8-byte accesses, latency-bound): 256-thread
     //    tiles, three resident per CU, and many short z-chunks (about 4096
     //    blocks) so that the CUs stay evenly loaded;
@@ -1163,6 +1164,12 @@ TileCfg choose_tiles(int nx, int ny, int nz, int dtype, int mode) {
         // blocks fill the GPU once (one 512-thread or two 256-thread blocks
         // per CU).
         zc = occupancy_zchunk(tiles, nz, want);
+        // A leapfrog grid this small fills the GPU only with the shortest
+        // chunks; there four waves per SIMD (1024-thread 256x16x1 tiles,
+        // one row per thread, same tile count) hide more latency than the
+        // two of 256x16x2 (256^3: 360 against 347 GPts/s, measured).
+        if (cand == c32 && mode == MODE_WAVE && t.tx == 256 && t.ry == 2 && zc <= 16 && nz > 16)
+            t.ry = 1;
     } else {
         const int chunks = (want + tiles - 1) / tiles;
         zc = (nz + chunks - 1) / chunks;
