@@ -751,10 +751,13 @@ __device__ __forceinline__ void star25_body(const SweepArgs &a, const int lin) {
                                              (eq[2][i] - eq[0][i]) * (q[j][5][i] - q[j][3][i]));
                     const float ae = eC[i] * a.dt;
                     const float bb = ae + a.alpha_dt;
-                    pn[i] = ((1.f - 0.5f * bb) * ps[i] - a.dt * G) / (1.f + 0.5f * bb);
+                    // the two quotients take the hardware reciprocal (1 ulp)
+                    // instead of a correctly rounded division: about 70
+                    // fewer instructions per plane in this compute-bound mode
+                    pn[i] = ((1.f - 0.5f * bb) * ps[i] - a.dt * G) * __builtin_amdgcn_rcpf(1.f + 0.5f * bb);
                     const float m = vv[j][i] * vv[j][i] * a.m_scale;
                     res[i] = ((2.f - ae * ae) * ctr[i] - (1.f - ae) * IO::dec(pp[j], 1.f)[i] +
-                              m * (acc[i] + 0.5f * (ps[i] + pn[i]))) / (1.f + ae);
+                              m * (acc[i] + 0.5f * (ps[i] + pn[i]))) * __builtin_amdgcn_rcpf(1.f + ae);
                 }
                 const int y = ybase + j;
                 for (int s = 0; s < a.src.n; ++s) {
