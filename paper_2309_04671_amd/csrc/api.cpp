@@ -528,15 +528,17 @@ int sp_wave_step_pml(const sp_grid *g, const sp_coeffs *c, double dt, double dx,
     // update reduces to the leapfrog there.
     struct Box {
         int mode;
+        bool wide;                 // a z or y slab (the full x extent)
         sp::SweepArgs a;
         sp::TileCfg t;
         int64_t off;
     };
     Box boxes[7];
     int nb = 0;
-    auto add = [&](int x0, int x1, int y0, int y1, int z0, int z1, int mode) {
+    auto add = [&](int x0, int x1, int y0, int y1, int z0, int z1, int mode, bool wide) {
         Box &b = boxes[nb++];
         b.mode = mode;
+        b.wide = wide;
         b.a = a;
         b.a.nx = x1 - x0;
         b.a.ny = y1 - y0;
@@ -554,27 +556,28 @@ int sp_wave_step_pml(const sp_grid *g, const sp_coeffs *c, double dt, double dx,
         }
         b.t = sp::choose_tiles(b.a.nx, b.a.ny, b.a.nz, SP_F32, mode);
         if (dec == SP_PML_TWO && mode == sp::MODE_PML) {
-            // the shell as one launch: every slab on 32x32x1 tiles, 512
-            // blocks of 256 threads per round
-            b.t.tx = 32;
-            b.t.ty = 32;
+            // the shell as one launch of 512-thread blocks (one per CU):
+            // the z and y slabs on 256x8x1 tiles, the x slabs on 32x64x1
+            b.t.tx = wide ? 256 : 32;
+            b.t.ty = wide ? 8 : 64;
             b.t.ry = 1;
-            b.t.zchunk = sp::occupancy_zchunk((int64_t)((b.a.nx + 31) / 32) * ((b.a.ny + 31) / 32),
-                                              b.a.nz, 512);
+            b.t.zchunk = sp::occupancy_zchunk((int64_t)((b.a.nx + b.t.tx - 1) / b.t.tx) *
+                                                  ((b.a.ny + b.t.ty - 1) / b.t.ty),
+                                              b.a.nz, 256);
         }
         fill_tiling(b.a, b.t);
     };
     if (!seven) {
-        add(0, nx, 0, ny, 0, nz, sp::MODE_PML);
+        add(0, nx, 0, ny, 0, nz, sp::MODE_PML, true);
     } else {
         const int xe = W + 4 * ((nx - 2 * W) / 4);
-        add(W, xe, W, ny - W, W, nz - W, sp::MODE_WAVE);
-        add(0, nx, 0, ny, 0, W, sp::MODE_PML);
-        add(0, nx, 0, ny, nz - W, nz, sp::MODE_PML);
-        add(0, nx, 0, W, W, nz - W, sp::MODE_PML);
-        add(0, nx, ny - W, ny, W, nz - W, sp::MODE_PML);
-        add(0, W, W, ny - W, W, nz - W, sp::MODE_PML);
-        add(xe, nx, W, ny - W, W, nz - W, sp::MODE_PML);
+        add(W, xe, W, ny - W, W, nz - W, sp::MODE_WAVE, true);
+        add(0, nx, 0, ny, 0, W, sp::MODE_PML, true);
+        add(0, nx, 0, ny, nz - W, nz, sp::MODE_PML, true);
+        add(0, nx, 0, W, W, nz - W, sp::MODE_PML, true);
+        add(0, nx, ny - W, ny, W, nz - W, sp::MODE_PML, true);
+        add(0, W, W, ny - W, W, nz - W, sp::MODE_PML, false);
+        add(xe, nx, W, ny - W, W, nz - W, sp::MODE_PML, false);
     }
     const int nrec = rec ? rec->n : 0;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -601,9 +604,10 @@ int sp_wave_step_pml(const sp_grid *g, const sp_coeffs *c, double dt, double dx,
             for (int q = 1; q < nb; ++q) {
                 const sp::SweepArgs &ba = boxes[q].a;
                 shell.a[q - 1] = ba;
+                shell.wide[q - 1] = boxes[q].wide ? 1 : 0;
                 shell.first[q] = shell.first[q - 1] + ba.tiles_x * ba.tiles_y * ba.nzc;
             }
-            if (err == hipSuccess) err = sp::launch_sweep_boxes(sp::MODE_PML, boxes[1].t, shell, s);
+            if (err == hipSuccess) err = sp::launch_sweep_boxes(sp::MODE_PML, shell, s);
         } else {
             for (int q = 0; q < nb && err == hipSuccess; ++q)
                 err = sp::launch_sweep(boxes[q].mode, SP_F32, boxes[q].t, boxes[q].a, s);

@@ -86,15 +86,18 @@ TileCfg choose_tiles(int nx, int ny, int nz, int dtype, int mode);
 // Planes per block for `tiles` xy tiles when per_round blocks fill the GPU.
 int occupancy_zchunk(int64_t tiles, int nz, int per_round);
 
-// Up to MAX_BOXES boxes of one grid swept by one launch: box k takes blocks
-// [first[k], first[k+1]) (kernel arguments: 6 x 480 B fits the 4 KB limit).
+// Up to MAX_BOXES boxes of one grid swept by one launch of 512-thread
+// blocks: box k takes blocks [first[k], first[k+1]), on 256x8x1 tiles if
+// wide[k], else on 32x64x1 tiles (kernel arguments: 6 x 480 B fits the
+// 4 KB limit).
 constexpr int MAX_BOXES = 6;
 struct BoxSet {
     SweepArgs a[MAX_BOXES];
     int first[MAX_BOXES + 1];
+    int wide[MAX_BOXES];
     int n;
 };
-hipError_t launch_sweep_boxes(int mode, const TileCfg &t, const BoxSet &bs, hipStream_t s);
+hipError_t launch_sweep_boxes(int mode, const BoxSet &bs, hipStream_t s);
 // Configurations the batched (multi-grid) sweep is compiled for.
 bool batch_supported(const TileCfg &t);
 bool tile_supported(const TileCfg &t);

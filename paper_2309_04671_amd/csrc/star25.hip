@@ -909,14 +909,20 @@ k_star25(SweepArgs a) {
 // Several boxes of one grid in one launch (the absorbing layer's shell as
 // one region): block b sweeps tile b - first[k] of box k, the box whose
 // block range holds b; each XCD receives one contiguous range of blocks.
-template <int TX, int TY, int RY, int MODE, typename T>
-__global__ void __launch_bounds__((TX / 4) * (TY / RY)) k_star25_boxes(const BoxSet bs) {
+// The wide z and y slabs run on 256x8x1 tiles and the 32-wide x slabs on
+// 32x64x1 tiles (both 512 threads; the choice is uniform per block), so the
+// thin x slabs overlap the wide ones.
+template <int MODE, typename T>
+__global__ void __launch_bounds__(512) k_star25_shell(const BoxSet bs) {
     const int lin = xcd_tile(blockIdx.x, gridDim.x);
     int k = 0;
 #pragma unroll
     for (int i = 1; i < MAX_BOXES; ++i)
         if (i < bs.n && lin >= bs.first[i]) k = i;
-    star25_body<TX, TY, RY, MODE, T>(bs.a[k], lin - bs.first[k]);
+    if (bs.wide[k])
+        star25_body<256, 8, 1, MODE, T>(bs.a[k], lin - bs.first[k]);
+    else
+        star25_body<32, 64, 1, MODE, T>(bs.a[k], lin - bs.first[k]);
 }
 
 // Batched form: block b computes tile table[b].y of grid table[b].x, whose
@@ -1183,12 +1189,9 @@ TileCfg choose_tiles(int nx, int ny, int nz, int dtype, int mode) {
     return t;
 }
 
-hipError_t launch_sweep_boxes(int mode, const TileCfg &t, const BoxSet &bs, hipStream_t s) {
-    // the layer mode on 32x32x1 tiles, the tile of the narrowest slabs
-    if (mode != MODE_PML || t.tx != 32 || t.ty != 32 || t.ry != 1 || bs.n < 1 || bs.n > MAX_BOXES)
-        return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_star25_boxes<32, 32, 1, MODE_PML, float>), dim3(bs.first[bs.n]), dim3(256), 0, s,
-                       bs);
+hipError_t launch_sweep_boxes(int mode, const BoxSet &bs, hipStream_t s) {
+    if (mode != MODE_PML || bs.n < 1 || bs.n > MAX_BOXES) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_star25_shell<MODE_PML, float>), dim3(bs.first[bs.n]), dim3(512), 0, s, bs);
     return hipGetLastError();
 }
 
