@@ -50,6 +50,11 @@ def _load():
     lib.ref_energy.restype = d
     lib.ref_adjoint_grad.argtypes = [i, i, i, _dp, d, d, _dp, i, i, _ip, _dp, i, _ip, _dp, _dp]
     lib.ref_adjoint_grad.restype = d
+    lib.ref_adjoint_grad_ckpt.argtypes = [i, i, i, _dp, d, d, _dp, i, i, _ip, _dp, i, _ip, _dp, i,
+                                          _dp, _dp]
+    lib.ref_adjoint_grad_ckpt.restype = d
+    lib.ref_pml_profile.argtypes = [i, i, i, i, d, _dp]
+    lib.ref_pml_profile.restype = None
     lib.ref_stencil_general.argtypes = [i, i, i, i, i, _dp, _dp, _dp]
     lib.ref_stencil_general.restype = None
     lib.ref_wave_pml_run.argtypes = [i, i, i, _dp, d, d, _dp, _dp, d, i, i, _ip, _dp, i, _ip, _dp,
@@ -163,6 +168,36 @@ def adjoint_grad(coeffs, v, dt, dx, nsteps, src, amp, rec, obs):
                                  _p(v), int(nsteps), len(src), _p(src, _ip), _p(amp),
                                  len(rec), _p(rec, _ip), _p(obs), _p(g))
     return J, g
+
+
+def adjoint_grad_ckpt(coeffs, v, dt, dx, nsteps, src, amp, rec, obs, ckpt, traces=False):
+    """The same J and dJ/dv with checkpointing (ref.c ``ref_adjoint_grad_ckpt``):
+    the pair (u^{n0-1}, u^{n0}) is kept every ``ckpt`` steps and each segment
+    recomputed, so memory is about 2 N/ckpt + ckpt fields.  Bit-identical to
+    ``adjoint_grad``.  With traces=True also returns the forward traces
+    R u^{n+1}, shape (nsteps, nrec)."""
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    nz, ny, nx = v.shape
+    src = np.ascontiguousarray(src, np.int32).reshape(-1, 3)
+    rec = np.ascontiguousarray(rec, np.int32).reshape(-1, 3)
+    amp = np.ascontiguousarray(amp, np.float64).reshape(int(nsteps), max(len(src), 1))
+    obs = np.ascontiguousarray(obs, np.float64)
+    g = np.zeros((nz, ny, nx), dtype=np.float64)
+    tr = np.zeros((int(nsteps), max(len(rec), 1)), dtype=np.float64)
+    J = _load().ref_adjoint_grad_ckpt(nx, ny, nz, _p(coeff_vector(coeffs)), float(dt), float(dx),
+                                      _p(v), int(nsteps), len(src), _p(src, _ip), _p(amp),
+                                      len(rec), _p(rec, _ip), _p(obs), int(ckpt), _p(tr), _p(g))
+    if traces:
+        return J, g, tr[:, :len(rec)]
+    return J, g
+
+
+def pml_profile(nx, ny, nz, width, eta_max) -> np.ndarray:
+    """Damping of the absorbing layer on the padded (nz+8, ny+8, nx+8) array
+    (ref.c ``ref_pml_profile``): eta_max * sum over axes (d_a / W)^2."""
+    out = np.zeros((nz + 2 * HALO, ny + 2 * HALO, nx + 2 * HALO))
+    _load().ref_pml_profile(int(nx), int(ny), int(nz), int(width), float(eta_max), _p(out))
+    return out
 
 
 def stencil_general(u, w, ndim: int, sweeps: int = 1, frame=None) -> np.ndarray:

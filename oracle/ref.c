@@ -161,6 +161,98 @@ double ref_energy(int nx, int ny, int nz, const double *c, double dt, double dx,
 }
 
 /*
+ * Shared steps of the two adjoint-gradient routines below.  Both use the
+ * same per-point operations in the same order, so the checkpointed routine
+ * reproduces the full-storage one bit for bit.
+ */
+
+/* m = (v dt / dx)^2 on the padded grid, zero on the halo. */
+static double *wave_m(int nx, int ny, int nz, double dt, double dx, const double *v)
+{
+    const double r = dt / dx;
+    double *m = (double *)calloc((size_t)padded_count(nx, ny, nz), sizeof(double));
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                double vv = v[((int64_t)z * ny + y) * nx + x];
+                m[at(nx, ny, x, y, z)] = (vv * r) * (vv * r);
+            }
+    return m;
+}
+
+/* Forward step n of Eq. 2 with the source of Algorithm 1 written through m:
+ *     un = 2 uc - up + m (L uc),   un[src] += m dx^2 amp[n]
+ * (m dx^2 amp = dt^2 v^2 amp).  lap is scratch. */
+static void fwd_step(int nx, int ny, int nz, const double *c, double dx, const double *m,
+                     const double *up, const double *uc, double *un, double *lap, int n,
+                     int nsrc, const int32_t *src, const double *amp)
+{
+    ref_laplacian(nx, ny, nz, c, uc, lap);
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                int64_t i = at(nx, ny, x, y, z);
+                un[i] = 2.0 * uc[i] - up[i] + m[i] * lap[i];
+            }
+    for (int s = 0; s < nsrc; ++s) {
+        int64_t i = at(nx, ny, src[3 * s], src[3 * s + 1], src[3 * s + 2]);
+        un[i] += m[i] * dx * dx * amp[(int64_t)n * nsrc + s];
+    }
+}
+
+/* Adjoint step for time index k, then its gradient term:
+ *     l0 = 2 l1 - l2 + L(m l1) + R^T res[k-1]          (lambda^k),
+ *     gm += l0 (L ukm1 + dx^2 amp[k-1] e_src)        (ukm1 = u^{k-1}).
+ * ml and lap are scratch. */
+static void adj_step(int nx, int ny, int nz, const double *c, double dx, const double *m,
+                     const double *l1, const double *l2, double *l0, const double *ukm1,
+                     double *gm, double *ml, double *lap, int k, int nsrc, const int32_t *src,
+                     const double *amp, int nrec, const int32_t *rec, const double *res)
+{
+    const int64_t np = padded_count(nx, ny, nz);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < np; ++i) ml[i] = m[i] * l1[i];
+    ref_laplacian(nx, ny, nz, c, ml, lap);
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                int64_t i = at(nx, ny, x, y, z);
+                l0[i] = 2.0 * l1[i] - l2[i] + lap[i];
+            }
+    for (int q = 0; q < nrec; ++q)
+        l0[at(nx, ny, rec[3 * q], rec[3 * q + 1], rec[3 * q + 2])] += res[(int64_t)(k - 1) * nrec + q];
+    ref_laplacian(nx, ny, nz, c, ukm1, lap);
+    for (int s = 0; s < nsrc; ++s) {
+        int64_t i = at(nx, ny, src[3 * s], src[3 * s + 1], src[3 * s + 2]);
+        lap[i] += dx * dx * amp[(int64_t)(k - 1) * nsrc + s];
+    }
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                int64_t i = at(nx, ny, x, y, z);
+                gm[i] += l0[i] * lap[i];
+            }
+}
+
+/* dJ/dv = dJ/dm 2 m / v on the interior (interior-dense output). */
+static void grad_to_v(int nx, int ny, int nz, const double *v, const double *m, const double *gm,
+                      double *grad_v)
+{
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                int64_t i = at(nx, ny, x, y, z);
+                double vv = v[((int64_t)z * ny + y) * nx + x];
+                grad_v[((int64_t)z * ny + y) * nx + x] = gm[i] * 2.0 * m[i] / vv;
+            }
+}
+
+/*
  * Misfit gradient by the discrete adjoint of the leapfrog, with every forward
  * state kept in memory (for small grids).  Forward (ref_wave_run semantics)
  * from zero states:
@@ -182,34 +274,13 @@ double ref_adjoint_grad(int nx, int ny, int nz, const double *c, double dt, doub
 {
     const int64_t np = padded_count(nx, ny, nz);
     const int N = nsteps;
-    const double r = dt / dx;
-    /* m on the padded grid, zero on the halo */
-    double *m = (double *)calloc((size_t)np, sizeof(double));
-    for (int z = 0; z < nz; ++z)
-        for (int y = 0; y < ny; ++y)
-            for (int x = 0; x < nx; ++x) {
-                double vv = v[((int64_t)z * ny + y) * nx + x];
-                m[at(nx, ny, x, y, z)] = (vv * r) * (vv * r);
-            }
+    double *m = wave_m(nx, ny, nz, dt, dx, v);
     /* all states u^{-1}..u^N: u[n+1] is u^n */
     double *u = (double *)calloc((size_t)np * (N + 2), sizeof(double));
     double *lap = (double *)calloc((size_t)np, sizeof(double));
 #define U(n) (u + (int64_t)((n) + 1) * np)
-    for (int n = 0; n < N; ++n) {
-        const double *uc = U(n), *up = U(n - 1);
-        double *un = U(n + 1);
-        ref_laplacian(nx, ny, nz, c, uc, lap);
-        for (int z = 0; z < nz; ++z)
-            for (int y = 0; y < ny; ++y)
-                for (int x = 0; x < nx; ++x) {
-                    int64_t i = at(nx, ny, x, y, z);
-                    un[i] = 2.0 * uc[i] - up[i] + m[i] * lap[i];
-                }
-        for (int s = 0; s < nsrc; ++s) {
-            int64_t i = at(nx, ny, src[3 * s], src[3 * s + 1], src[3 * s + 2]);
-            un[i] += m[i] * dx * dx * amp[(int64_t)n * nsrc + s];
-        }
-    }
+    for (int n = 0; n < N; ++n)
+        fwd_step(nx, ny, nz, c, dx, m, U(n - 1), U(n), U(n + 1), lap, n, nsrc, src, amp);
     /* residuals and misfit */
     double *res = (double *)calloc((size_t)N * (nrec > 0 ? nrec : 1), sizeof(double));
     double J = 0.0;
@@ -227,41 +298,128 @@ double ref_adjoint_grad(int nx, int ny, int nz, const double *c, double dt, doub
     double *ml = (double *)calloc((size_t)np, sizeof(double));
     double *gm = (double *)calloc((size_t)np, sizeof(double));
     for (int k = N; k >= 1; --k) {
-        for (int64_t i = 0; i < np; ++i) ml[i] = m[i] * l1[i];
-        ref_laplacian(nx, ny, nz, c, ml, lap);
-        for (int z = 0; z < nz; ++z)
-            for (int y = 0; y < ny; ++y)
-                for (int x = 0; x < nx; ++x) {
-                    int64_t i = at(nx, ny, x, y, z);
-                    l0[i] = 2.0 * l1[i] - l2[i] + lap[i];
-                }
-        for (int q = 0; q < nrec; ++q)
-            l0[at(nx, ny, rec[3 * q], rec[3 * q + 1], rec[3 * q + 2])] +=
-                res[(int64_t)(k - 1) * nrec + q];
-        /* dJ/dm += lambda^k (L u^{k-1} + dx^2 amp[k-1] e_src) */
-        ref_laplacian(nx, ny, nz, c, U(k - 1), lap);
-        for (int s = 0; s < nsrc; ++s) {
-            int64_t i = at(nx, ny, src[3 * s], src[3 * s + 1], src[3 * s + 2]);
-            lap[i] += dx * dx * amp[(int64_t)(k - 1) * nsrc + s];
-        }
-        for (int z = 0; z < nz; ++z)
-            for (int y = 0; y < ny; ++y)
-                for (int x = 0; x < nx; ++x) {
-                    int64_t i = at(nx, ny, x, y, z);
-                    gm[i] += l0[i] * lap[i];
-                }
+        adj_step(nx, ny, nz, c, dx, m, l1, l2, l0, U(k - 1), gm, ml, lap, k, nsrc, src, amp,
+                 nrec, rec, res);
         double *t = l2; l2 = l1; l1 = l0; l0 = t;
     }
-    for (int z = 0; z < nz; ++z)
-        for (int y = 0; y < ny; ++y)
-            for (int x = 0; x < nx; ++x) {
-                int64_t i = at(nx, ny, x, y, z);
-                double vv = v[((int64_t)z * ny + y) * nx + x];
-                grad_v[((int64_t)z * ny + y) * nx + x] = gm[i] * 2.0 * m[i] / vv;
-            }
+    grad_to_v(nx, ny, nz, v, m, gm, grad_v);
 #undef U
     free(m); free(u); free(lap); free(res); free(l1); free(l2); free(l0); free(ml); free(gm);
     return J;
+}
+
+/*
+ * The same misfit gradient with checkpointing, for grids whose N states do
+ * not fit in memory: the forward pass keeps only the pair (u^{n0-1}, u^{n0})
+ * at every segment start n0 = 0, C, 2C, ... (C = ckpt, about sqrt(N) for the
+ * least memory), and the residuals.  The adjoint then walks the segments
+ * from the last to the first; for each it recomputes u^{n0+1} .. u^{n0+L-1}
+ * from the segment's pair (L = min(C, N - n0)) with the same forward step,
+ * and takes the adjoint steps k = n0+L .. n0+1, which need u^{k-1}.
+ * Memory: 2 N/C + C + 8 padded fields instead of N + 8.  Every state and
+ * every adjoint step is computed by the same operations as in
+ * ref_adjoint_grad, so the results are bit-identical to it.
+ * traces (optional, may be NULL): the forward traces R u^{n+1}, [N][nrec].
+ * Returns J; grad_v is interior-dense (nz, ny, nx).
+ */
+double ref_adjoint_grad_ckpt(int nx, int ny, int nz, const double *c, double dt, double dx,
+                             const double *v, int nsteps,
+                             int nsrc, const int32_t *src, const double *amp,
+                             int nrec, const int32_t *rec, const double *obs,
+                             int ckpt, double *traces, double *grad_v)
+{
+    const int64_t np = padded_count(nx, ny, nz);
+    const int N = nsteps;
+    const int C = ckpt < 1 ? 1 : ckpt;
+    const int nseg = N > 0 ? (N + C - 1) / C : 0;
+    double *m = wave_m(nx, ny, nz, dt, dx, v);
+    double *lap = (double *)calloc((size_t)np, sizeof(double));
+    /* segment-start pairs: pair[2j] = u^{jC-1}, pair[2j+1] = u^{jC} */
+    double *pair = (double *)calloc((size_t)np * 2 * (nseg > 0 ? nseg : 1), sizeof(double));
+    /* segment ring: ring[i] = u^{n0-1+i}, i = 0..C */
+    double *ring = (double *)calloc((size_t)np * (C + 1), sizeof(double));
+    double *res = (double *)calloc((size_t)N * (nrec > 0 ? nrec : 1), sizeof(double));
+#define RING(i) (ring + (int64_t)(i) * np)
+#define PAIR(j, h) (pair + ((int64_t)2 * (j) + (h)) * np)
+    /* forward pass from zero states: three rotating buffers in the ring */
+    double J = 0.0;
+    {
+        double *b[3] = {RING(0), RING(1), RING(2 <= C ? 2 : 0)};
+        double *extra = NULL;
+        if (C < 2) {                    /* C = 1: the ring has two fields only */
+            extra = (double *)calloc((size_t)np, sizeof(double));
+            b[2] = extra;
+        }
+        double *up = b[0], *uc = b[1], *un = b[2];
+        for (int n = 0; n < N; ++n) {
+            if (n % C == 0) {
+                memcpy(PAIR(n / C, 0), up, (size_t)np * sizeof(double));
+                memcpy(PAIR(n / C, 1), uc, (size_t)np * sizeof(double));
+            }
+            fwd_step(nx, ny, nz, c, dx, m, up, uc, un, lap, n, nsrc, src, amp);
+            for (int q = 0; q < nrec; ++q) {
+                double t = un[at(nx, ny, rec[3 * q], rec[3 * q + 1], rec[3 * q + 2])];
+                double d = t - obs[(int64_t)n * nrec + q];
+                if (traces) traces[(int64_t)n * nrec + q] = t;
+                res[(int64_t)n * nrec + q] = d;
+                J += 0.5 * d * d;
+            }
+            double *t = up; up = uc; uc = un; un = t;
+        }
+        free(extra);
+    }
+    /* adjoint pass, segments last to first */
+    double *l1 = (double *)calloc((size_t)np, sizeof(double)); /* lambda^{k+1} */
+    double *l2 = (double *)calloc((size_t)np, sizeof(double)); /* lambda^{k+2} */
+    double *l0 = (double *)calloc((size_t)np, sizeof(double)); /* lambda^k     */
+    double *ml = (double *)calloc((size_t)np, sizeof(double));
+    double *gm = (double *)calloc((size_t)np, sizeof(double));
+    for (int j = nseg - 1; j >= 0; --j) {
+        const int n0 = j * C;
+        const int L = N - n0 < C ? N - n0 : C;
+        memcpy(RING(0), PAIR(j, 0), (size_t)np * sizeof(double));
+        memcpy(RING(1), PAIR(j, 1), (size_t)np * sizeof(double));
+        for (int i = 0; i + 1 < L; ++i)     /* u^{n0+i+1} from u^{n0+i-1}, u^{n0+i} */
+            fwd_step(nx, ny, nz, c, dx, m, RING(i), RING(i + 1), RING(i + 2), lap, n0 + i,
+                     nsrc, src, amp);
+        for (int k = n0 + L; k >= n0 + 1; --k) {
+            adj_step(nx, ny, nz, c, dx, m, l1, l2, l0, RING(k - n0), gm, ml, lap, k, nsrc, src,
+                     amp, nrec, rec, res);
+            double *t = l2; l2 = l1; l1 = l0; l0 = t;
+        }
+    }
+    grad_to_v(nx, ny, nz, v, m, gm, grad_v);
+#undef RING
+#undef PAIR
+    free(m); free(lap); free(pair); free(ring); free(res);
+    free(l1); free(l2); free(l0); free(ml); free(gm);
+    return J;
+}
+
+/*
+ * Damping profile of the absorbing layer, on the padded array (frame
+ * included): for a layer of W cells on every face,
+ *     eta = eta_max * sum over axes (d_a / W)^2,
+ *     d_a = max(0, W - 1 - a, a - (n_a - W)),  a = -4 .. n_a + 3,
+ * the depth of index a into the layer (0 on the layer's innermost cells and
+ * on the inner box, growing into the halo frame).
+ */
+void ref_pml_profile(int nx, int ny, int nz, int width, double eta_max, double *eta)
+{
+    const double W = (double)width;
+    for (int z = -H; z < nz + H; ++z)
+        for (int y = -H; y < ny + H; ++y)
+            for (int x = -H; x < nx + H; ++x) {
+                const int a[3] = {x, y, z}, n[3] = {nx, ny, nz};
+                double s = 0.0;
+                for (int k = 0; k < 3; ++k) {
+                    int d = 0;
+                    if (width - 1 - a[k] > d) d = width - 1 - a[k];
+                    if (a[k] - (n[k] - width) > d) d = a[k] - (n[k] - width);
+                    s += ((double)d / W) * ((double)d / W);
+                }
+                eta[at(nx, ny, x, y, z)] = eta_max * s;
+            }
 }
 
 int ref_num_threads(void)

@@ -45,7 +45,7 @@ def test_profile_kernel_matches_the_profile(gpu_lib):
         lib.sp_pml_profile(g, W, 123.5, E.ptr)
         torch.cuda.synchronize()
         got = E.padded().cpu().numpy().astype(np.float64)
-        ref = synth.pml_profile(nx, ny, nz, W, 123.5)
+        ref = oracle.pml_profile(nx, ny, nz, W, 123.5)
         # FP32 evaluation: three squares, two sums and a product
         assert np.all(np.abs(got - ref) <= 1e-6 * np.abs(ref))
 

@@ -129,11 +129,41 @@ def test_frequency_shift_makes_long_runs_decay():
     assert unshifted[-1] > 100 * min(unshifted)          # the zero-frequency mode grows
 
 
-def test_profile_vanishes_on_the_inner_box_and_its_neighbours():
+@pytest.mark.parametrize("profile", ["oracle", "synth"])
+def test_profile_vanishes_on_the_inner_box_and_its_neighbours(profile):
     n, W = 30, 6
-    e = synth.pml_profile(n, n, n, W, 100.0)
+    e = (oracle.pml_profile if profile == "oracle" else synth.pml_profile)(n, n, n, W, 100.0)
     inner = e[4 + W - 1:4 + n - W + 1, 4 + W - 1:4 + n - W + 1, 4 + W - 1:4 + n - W + 1]
     assert not inner.any()
     # outermost interior cell of a face centre: depth W-1 on one axis
     assert e[4 + 0, 4 + n // 2, 4 + n // 2] == pytest.approx(100.0 * ((W - 1) / W) ** 2)
     assert synth.pml_eta_max(2000.0, 10, 10.0) == pytest.approx(3 * 2000.0 * np.log(1e3) / 200.0)
+
+
+def test_oracle_profile_closed_forms():
+    # eta = eta_max * sum over axes (d_a / W)^2 with d_a the depth into the
+    # layer, checked cell by cell against values worked out by hand on a
+    # ragged grid (a wrong axis, offset or square fails one of them).
+    nx, ny, nz, W, emax = 20, 13, 17, 4, 8.0
+    e = oracle.pml_profile(nx, ny, nz, W, emax)
+    assert e.shape == (nz + 8, ny + 8, nx + 8)
+
+    def at(x, y, z):
+        return e[z + 4, y + 4, x + 4]
+    # inner box [W-1, n-W] on every axis: zero
+    assert at(W - 1, W - 1, W - 1) == 0.0 and at(nx - W, ny - W, nz - W) == 0.0
+    # one layer axis at a time: depth W-1-a (low side), a-(n-W) (high side)
+    assert at(0, 6, 8) == emax * (3 / 4) ** 2
+    assert at(nx - 1, 6, 8) == emax * (3 / 4) ** 2
+    assert at(-4, 6, 8) == emax * (7 / 4) ** 2              # halo frame: depth W + 3
+    assert at(9, ny + 3, 8) == emax * (7 / 4) ** 2
+    assert at(9, 6, 1) == emax * (2 / 4) ** 2
+    assert at(9, 6, nz - 2) == emax * (2 / 4) ** 2
+    # an edge and a corner sum the axes
+    assert at(1, 0, 8) == emax * ((2 / 4) ** 2 + (3 / 4) ** 2)
+    assert at(-4, -4, -4) == pytest.approx(3 * emax * (7 / 4) ** 2, rel=1e-15)
+    # mirror symmetry on each axis, and a transposed grid gives the transpose
+    assert np.array_equal(e, e[::-1, :, :]) and np.array_equal(e, e[:, ::-1, :])
+    assert np.array_equal(e, e[:, :, ::-1])
+    et = oracle.pml_profile(nz, ny, nx, W, emax)
+    assert np.array_equal(et, np.transpose(e, (2, 1, 0)))

@@ -182,3 +182,20 @@ def test_adjoint_misfit_matches_forward_traces():
     assert J0 <= 1e-20 * J
     J1, g1 = oracle.adjoint_grad(co, v, dt, dx, steps, src, amp, rec, obs)
     assert np.max(np.abs(g0)) <= 1e-9 * np.max(np.abs(g1))
+
+
+@pytest.mark.parametrize("ckpt", [1, 7, 60])
+def test_checkpointed_adjoint_is_bit_identical(ckpt):
+    # The checkpointed gradient keeps only segment-start pairs and recomputes
+    # each segment; with C = 7 the last segment is ragged (60 = 8 * 7 + 4).
+    # Same operations in the same order as the full-storage adjoint, which
+    # the finite-difference pin above checks: the results must be identical.
+    co, v, dt, dx, steps, src, amp, rec, obs = _adjoint_case(n=24, steps=60, seed=5)
+    J, g = oracle.adjoint_grad(co, v, dt, dx, steps, src, amp, rec, obs)
+    Jc, gc, tr = oracle.adjoint_grad_ckpt(co, v, dt, dx, steps, src, amp, rec, obs, ckpt,
+                                          traces=True)
+    assert Jc == J and np.array_equal(gc, g) and np.any(g != 0)
+    # its traces are the forward run's (up to the rounding of the injection)
+    fwd = oracle.wave_run(co, v, dt, dx, steps, src=src, amp=amp, rec=rec)["traces"]
+    assert np.max(np.abs(tr - fwd)) <= 1e-12 * np.max(np.abs(fwd))
+    assert np.isclose(Jc, 0.5 * np.sum((tr - obs) ** 2), rtol=1e-13, atol=0)
