@@ -244,8 +244,13 @@ int sp_wave_run_states(const sp_grid *g, const sp_coeffs *c, double dt, double d
 
 /*
  * sp_wave_adjoint_step -- `nsteps` steps of the discrete adjoint of the
- * leapfrog for a misfit L(traces), in the scaled variable nu = m * lambda
- * (FP32 grids only).  With g_k = dL/dtraces row k (the receiver samples of
+ * leapfrog of Eq. 2 (Sec. 2.2; time loop of Algorithm 1: update, then the
+ * source) for a misfit L(traces), in the scaled variable nu = m * lambda
+ * (FP32 grids only).  The adjoint is derived from the discrete update, not
+ * given by the paper: transposing u^{n+1} = 2u^n - u^{n-1} + m L u^n + m dx^2
+ * f^n e_src over all steps gives the backward recurrence for lambda, and
+ * since L is symmetric (zero halo) nu = m lambda follows the same leapfrog
+ * as the forward field.  With g_k = dL/dtraces row k (the receiver samples of
  * u^{k+1}), one adjoint step for time index k (k = N .. 1) computes
  *     nu^k = 2 nu^{k+1} - nu^{k+2} + m * (L nu^{k+1}) + m * R^T g_{k-1}
  * and accumulates, in FP64,
@@ -273,13 +278,15 @@ int sp_grad_finish(const sp_grid *gv, const float *v, const double *G, float *ou
                    void *stream);
 
 /*
- * sp_energy -- discrete energy between u0 = u^n and u1 = u^{n+1} (FP32
- * grids), accumulated in FP64:
+ * sp_energy -- discrete energy of the leapfrog of Eq. 2 (Sec. 2.2) between
+ * u0 = u^n and u1 = u^{n+1} (FP32 grids), accumulated in FP64:
  *     E = sum (u1 - u0)^2 / m - sum u1 * (L u0),   m = (v dt / dx)^2,
- * which the source-free leapfrog conserves exactly when L is symmetric (zero
- * halo).  Writes one double to *out (DEVICE).  ws: DEVICE workspace of
- * sp_energy_ws_bytes(g) bytes (per-block partial sums, added in a fixed
- * order, so the result is deterministic).
+ * with L the star of Eq. 3.  Taking the inner product of the Eq. 2 update
+ * with (u^{n+1} - u^{n-1}) / m shows that the source-free leapfrog conserves
+ * E exactly when L is symmetric (zero halo).  Writes one double to *out
+ * (DEVICE, 8-byte aligned).  ws: DEVICE workspace of sp_energy_ws_bytes(g)
+ * bytes (per-block partial sums, added in a fixed order, so the result is
+ * deterministic).
  */
 int64_t sp_energy_ws_bytes(const sp_grid *g);
 int sp_energy(const sp_grid *g, const sp_coeffs *c, double dt, double dx,

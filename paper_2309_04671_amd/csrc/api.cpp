@@ -730,6 +730,42 @@ int sp_grad_finish(const sp_grid *gv, const float *v, const double *G, float *ou
     return ok();
 }
 
+}  // extern "C"
+
+namespace {
+
+// Validation and arguments shared by the two energy entry points.
+int energy_prep(const char *who, const sp_grid *g, const sp_coeffs *c, double dt, double dx,
+                const sp_grid *gv, const float *v, const void *u0, const void *u1, double *out,
+                sp::SweepArgs *a, sp::TileCfg *t, int *nblk) {
+    if (int e = prep_wave(who, g, c, dt, dx, gv, v, nullptr, nullptr, a, t)) return e;
+    if (g->dtype != SP_F32) return fail(SP_EUNSUPPORTED, "%s: FP32 grids only", who);
+    if (!u0 || !u1 || !out) return fail(SP_EINVAL, "%s: NULL argument", who);
+    if (!aligned16(u0) || !aligned16(u1) || (reinterpret_cast<uintptr_t>(out) & 7u))
+        return fail(SP_EINVAL, "%s: misaligned pointer", who);
+    a->u = static_cast<const float *>(u0) + g->origin;
+    a->prev = static_cast<const float *>(u1) + g->origin;
+    *nblk = a->tiles_x * a->tiles_y * a->nzc;
+    return SP_OK;
+}
+
+// MODE_ENERGY sweep writing one FP64 partial per block into `partial`, then
+// their sum in block order into *out.  Every partial is written before it
+// is read, so `partial` needs no clearing.
+int energy_launch(const char *who, sp::SweepArgs &a, const sp::TileCfg &t, int nblk,
+                  double *partial, double *out, void *stream) {
+    a.gacc = partial;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t err = sp::launch_sweep(sp::MODE_ENERGY, SP_F32, t, a, s);
+    if (err == hipSuccess) err = sp::launch_sum(partial, nblk, out, s);
+    if (err != hipSuccess) return fail(SP_EDEVICE, "%s: %s", who, hipGetErrorString(err));
+    return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
 int64_t sp_energy_ws_bytes(const sp_grid *g) {
     if (!g || g->nx < 1 || g->ny < 1 || g->nz < 1) return 0;
     // upper bound over every compiled tile shape (smallest: 64 x 8) and z-chunk
@@ -740,21 +776,12 @@ int sp_energy(const sp_grid *g, const sp_coeffs *c, double dt, double dx, const 
               const float *v, const void *u0, const void *u1, double *out, void *ws, void *stream) {
     sp::SweepArgs a;
     sp::TileCfg t;
-    if (int e = prep_wave("sp_energy", g, c, dt, dx, gv, v, nullptr, nullptr, &a, &t)) return e;
-    if (g->dtype != SP_F32) return fail(SP_EUNSUPPORTED, "sp_energy: FP32 grids only");
-    if (!u0 || !u1 || !out || !ws) return fail(SP_EINVAL, "sp_energy: NULL argument");
-    if (!aligned16(u0) || !aligned16(u1) || (reinterpret_cast<uintptr_t>(ws) & 7u))
-        return fail(SP_EINVAL, "sp_energy: misaligned pointer");
-    const int nblk = a.tiles_x * a.tiles_y * a.nzc;
+    int nblk = 0;
+    if (int e = energy_prep("sp_energy", g, c, dt, dx, gv, v, u0, u1, out, &a, &t, &nblk)) return e;
+    if (!ws) return fail(SP_EINVAL, "sp_energy: NULL argument");
+    if (reinterpret_cast<uintptr_t>(ws) & 7u) return fail(SP_EINVAL, "sp_energy: misaligned pointer");
     if ((int64_t)nblk * 8 > sp_energy_ws_bytes(g)) return fail(SP_ENOMEM, "sp_energy: workspace too small");
-    a.u = static_cast<const float *>(u0) + g->origin;
-    a.prev = static_cast<const float *>(u1) + g->origin;
-    a.gacc = static_cast<double *>(ws);
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t err = sp::launch_sweep(sp::MODE_ENERGY, SP_F32, t, a, s);
-    if (err == hipSuccess) err = sp::launch_sum(static_cast<double *>(ws), nblk, out, s);
-    if (err != hipSuccess) return fail(SP_EDEVICE, "sp_energy: %s", hipGetErrorString(err));
-    return ok();
+    return energy_launch("sp_energy", a, t, nblk, static_cast<double *>(ws), out, stream);
 }
 
 }  // extern "C"

@@ -63,3 +63,22 @@ def oracle_wave_at(prev_pad, cur_pad, v, coeffs, dt, dx, pts, src=None, amp_row=
                             src=s, amp=a, prev=patch(prev_pad, x, y, z), cur=patch(cur_pad, x, y, z))
         out[k] = r["cur"][4, 4, 4]
     return out
+
+
+def errors_chunked(got, ref, chunk=32) -> dict:
+    """errors() of two (nz, ny, nx) arrays, accumulated over z-chunks so that
+    full-size fields need no full-size FP64 temporaries.  The sums are FP64."""
+    nz = got.shape[0]
+    sd = sr = 0.0
+    mx = 0.0
+    for z0 in range(0, nz, chunk):
+        a = np.asarray(got[z0:z0 + chunk], dtype=np.float64)
+        b = np.asarray(ref[z0:z0 + chunk], dtype=np.float64)
+        d = a - b
+        sd += float(np.sum(d * d))
+        sr += float(np.sum(b * b))
+        if d.size:
+            mx = max(mx, float(np.max(np.abs(d))))
+    n = got.size
+    return {"rel_l2": float(np.sqrt(sd)) / (float(np.sqrt(sr)) if sr > 0 else 1.0),
+            "max_abs": mx, "rmsd": float(np.sqrt(sd / n)) if n else 0.0}

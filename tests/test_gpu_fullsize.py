@@ -1,0 +1,123 @@
+"""Full-field parity at the benchmark sizes, in the launch configurations the
+benchmark times: every point of the output, not samples.
+
+ * FP32 leapfrog, 1024x1024x512 (layered model, Ricker source at the centre,
+   CFL 0.4): the sweeps of steps 1, 250 and 500 of the actual run.  Before
+   each of them the GPU state (u^{n-1}, u^n) is copied out, widened to FP64,
+   and the oracle takes one step from it (the per-sweep reading of the
+   error metric); all 536,870,912 points within rel-L2 1e-5 (spec bar),
+   with max-abs and RMSD reported.
+ * 25-point apply at 1024x1024x512 from U[-1, 1]: all points, rel-L2 1e-5.
+ * FP16 and BF16 storage at 512^3 (the storage-form workload): one step from
+   the state the real run reaches after 300 steps, against the storage
+   emulation of the same stored state: new slab scales equal, every stored
+   value within 1 ulp of the format plus the kernel's FP32 bound.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import lowp
+import synth
+from tests.gpu_util import errors, errors_chunked
+
+pytestmark = pytest.mark.gpu
+
+TOL_SWEEP = 1e-5
+
+
+def test_c1_full_field_per_sweep(gpu_lib):
+    from paper_2309_04671_amd import fields, lib
+    nx, ny, nz, nt = 1024, 1024, 512, 500
+    g = lib.grid_init(nx, ny, nz)
+    v = synth.layered_velocity(nx, ny, nz, 0)
+    V = fields.Field(g).set_interior(v)
+    dx = 10.0
+    dt = synth.cfl_dt(v, dx)
+    co = synth.star25_coeffs()
+    src_xyz = np.array([[nx // 2, ny // 2, nz // 2]], np.int32)
+    amp = torch.tensor(synth.ricker(nt, dt, 15.0)[:, None], dtype=torch.float32, device="cuda")
+    src = lib.make_sources(src_xyz, amp.data_ptr(), 1)
+    amp64 = amp.cpu().double().numpy()
+    ws = fields.WaveState(g)
+    for s in (1, 250, 500):
+        # advance to u^{s-1}; the next sweep (step s-1 -> s) is the one checked
+        k = s - 1 - ws.st.step
+        if k > 0:
+            lib.sp_wave_step(g, lib.coeffs(co), dt, dx, g, V.ptr, ws.st, k, src=src)
+        torch.cuda.synchronize()
+        prev = oracle.padded(ws.prev().get_interior())
+        cur = oracle.padded(ws.cur().get_interior())
+        lib.sp_wave_step(g, lib.coeffs(co), dt, dx, g, V.ptr, ws.st, 1, src=src)
+        torch.cuda.synchronize()
+        got = ws.cur().get_interior()
+        r = oracle.wave_run(co, v, dt, dx, 1, src=src_xyz, amp=amp64[s - 1:s], prev=prev, cur=cur)
+        del prev, cur
+        ref = oracle.interior(r["cur"])
+        e = errors_chunked(got, ref)
+        print("1024x1024x512 sweep %d, all points vs oracle: %s (peak %.3e)"
+              % (s, e, float(np.max(np.abs(got)))))
+        del got, r, ref
+        assert e["rel_l2"] <= TOL_SWEEP, (s, e)
+    assert ws.st.step == nt
+
+
+def test_apply_full_field(gpu_lib):
+    from paper_2309_04671_amd import fields, lib
+    nx, ny, nz = 1024, 1024, 512
+    g = lib.grid_init(nx, ny, nz)
+    u = synth.uniform_field((nz, ny, nx), 17)
+    U, W = fields.Field(g).set_interior(u), fields.Field(g)
+    co = synth.star25_coeffs()
+    assert lib.sp_stencil_apply(g, lib.coeffs(co), 1, U.ptr, W.ptr) == 1
+    torch.cuda.synchronize()
+    got = W.get_interior()
+    ref = oracle.laplacian(oracle.padded(u), co)
+    e = errors_chunked(got, ref)
+    print("1024x1024x512 apply, all points vs oracle:", e)
+    assert e["rel_l2"] <= TOL_SWEEP
+
+
+@pytest.mark.parametrize("fmt", ["f16", "bf16"])
+def test_c2_full_field_single_step(gpu_lib, fmt):
+    from paper_2309_04671_amd import fields, lib
+    n, n0 = 512, 300
+    dtype = {"f16": lib.SP_F16, "bf16": lib.SP_BF16}[fmt]
+    g = lib.grid_init(n, n, n, dtype)
+    gv = lib.grid_init(n, n, n)
+    v = synth.layered_velocity(n, n, n, 0)
+    V = fields.Field(gv).set_interior(v)
+    dx = 10.0
+    dt = synth.cfl_dt(v, dx)
+    co = synth.star25_coeffs()
+    src_xyz = np.array([[n // 2, n // 2, n // 2]], np.int32)
+    amp = torch.tensor(synth.ricker(n0 + 1, dt, 15.0)[:, None], dtype=torch.float32, device="cuda")
+    src = lib.make_sources(src_xyz, amp.data_ptr(), 1)
+    ws = fields.WaveState(g)
+    lib.sp_wave_step(g, lib.coeffs(co), dt, dx, gv, V.ptr, ws.st, n0, src=src)
+    torch.cuda.synchronize()
+    # the stored state (u^{n0-1}, u^{n0}) and its slab records
+    q_prev = ws.prev().get_interior().astype(np.float64)
+    q_cur = ws.cur().get_interior().astype(np.float64)
+    # slab records: scale and the FP32 maximum (stored as its IEEE bits)
+    s_prev, a_prev = (t.cpu().numpy().copy() for t in ws.slot(n0 - 1))
+    s_cur, a_cur = (t.cpu().numpy().copy() for t in ws.slot(n0))
+    lib.sp_wave_step(g, lib.coeffs(co), dt, dx, gv, V.ptr, ws.st, 1, src=src)
+    torch.cuda.synchronize()
+    q_gpu = ws.cur().get_interior().astype(np.float64)
+    s_gpu = ws.slot(n0 + 1)[0].cpu().numpy()
+    amp_row = amp[n0].cpu().numpy()
+    q_ref, s_ref, _, _ = lowp.step(co, v, dt, dx, fmt, q_prev, s_prev, a_prev, q_cur, s_cur, a_cur,
+                                   src=src_xyz, amp_row=amp_row)
+    del q_prev, q_cur
+    assert np.array_equal(s_gpu, s_ref)
+    d = np.abs(q_gpu - q_ref)
+    ulp = lowp.ulp(q_ref, fmt)
+    ratio = float(np.max(d / ulp))
+    exact = float(np.mean(d == 0))
+    print(fmt, "512^3 after %d steps, all points: max |dq| / ulp = %.3f, exact fraction %.5f, "
+          "nonzero fraction %.3f" % (n0, ratio, exact, float(np.mean(q_ref != 0))))
+    assert np.all(d <= ulp + 2.0 ** -4)
+    assert exact > 0.95

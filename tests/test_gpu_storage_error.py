@@ -13,11 +13,8 @@ Bars (about three times the errors measured on MI355X):
  * FP16 storage: rel-L2 <= 4e-2 and |drift| <= 1e-2;
  * BF16 storage: rel-L2 <= 1 and |drift| <= 0.2 (its 8-bit significand does
    not survive 1000 steps; the bar only guards against a broken path).
-The 512^3 case needs about 105 s of FP64 oracle on 16 host threads and runs
-only when SP_LONG_TESTS=1.
+The 512^3 case needs about 105 s of FP64 oracle on 16 host threads.
 """
-
-import os
 
 import numpy as np
 import pytest
@@ -96,7 +93,5 @@ def test_storage_forms_vs_oracle_128(gpu_lib):
     _check(128)
 
 
-@pytest.mark.skipif(os.environ.get("SP_LONG_TESTS") != "1",
-                    reason="about 105 s of FP64 oracle; set SP_LONG_TESTS=1")
 def test_storage_forms_vs_oracle_512(gpu_lib):
     _check(512)
