@@ -64,6 +64,8 @@ def _load():
     lib.ref_num_threads.restype = i
     lib.ref_set_num_threads.argtypes = [i]
     lib.ref_set_num_threads.restype = None
+    lib.ref_set_progress.argtypes = [i]
+    lib.ref_set_progress.restype = None
     _lib = lib
     return lib
 
@@ -101,6 +103,12 @@ def num_threads() -> int:
 def set_num_threads(n: int) -> None:
     """Threads of the oracle's parallel loops (timing only)."""
     _load().ref_set_num_threads(int(n))
+
+
+def set_progress(every: int) -> None:
+    """Print a line on stderr every ``every`` time steps of the long runs
+    (leapfrog and checkpointed adjoint); 0 turns it off."""
+    _load().ref_set_progress(int(every))
 
 
 def laplacian(u_pad, coeffs) -> np.ndarray:

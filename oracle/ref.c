@@ -22,10 +22,28 @@
  */
 #include <math.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
 #define H 4
+
+/* Progress lines on stderr every `progress_every` time steps of the long
+ * runs (0: none).  Reporting only; no result depends on it. */
+static int progress_every = 0;
+
+void ref_set_progress(int every)
+{
+    progress_every = every > 0 ? every : 0;
+}
+
+static void progress(const char *what, int done, int total)
+{
+    if (progress_every > 0 && done % progress_every == 0) {
+        fprintf(stderr, "oracle %s: %d of %d steps\n", what, done, total);
+        fflush(stderr);
+    }
+}
 
 static inline int64_t at(int nx, int ny, int x, int y, int z)
 {
@@ -118,6 +136,7 @@ void ref_wave_run(int nx, int ny, int nz, const double *c, double dt, double dx,
             traces[(int64_t)n * nrec + q] = up[at(nx, ny, x, y, z)];
         }
         int t = ip; ip = ic; ic = t;
+        progress("leapfrog", n + 1, nsteps);
     }
     /* the newest state is bufs[ic]; put u^N in cur and u^{N-1} in prev */
     if (bufs[ic] != cur) {
@@ -365,6 +384,7 @@ double ref_adjoint_grad_ckpt(int nx, int ny, int nz, const double *c, double dt,
                 J += 0.5 * d * d;
             }
             double *t = up; up = uc; uc = un; un = t;
+            progress("adjoint, forward pass", n + 1, N);
         }
         free(extra);
     }
@@ -386,6 +406,7 @@ double ref_adjoint_grad_ckpt(int nx, int ny, int nz, const double *c, double dt,
             adj_step(nx, ny, nz, c, dx, m, l1, l2, l0, RING(k - n0), gm, ml, lap, k, nsrc, src,
                      amp, nrec, rec, res);
             double *t = l2; l2 = l1; l1 = l0; l0 = t;
+            progress("adjoint, backward pass", N - k + 1, N);
         }
     }
     grad_to_v(nx, ny, nz, v, m, gm, grad_v);

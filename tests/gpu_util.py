@@ -5,6 +5,8 @@ Inputs come from ``synth``; expected values come from ``oracle`` only.
 
 from __future__ import annotations
 
+import contextlib
+
 import numpy as np
 
 import oracle
@@ -82,3 +84,15 @@ def errors_chunked(got, ref, chunk=32) -> dict:
     n = got.size
     return {"rel_l2": float(np.sqrt(sd)) / (float(np.sqrt(sr)) if sr > 0 else 1.0),
             "max_abs": mx, "rmsd": float(np.sqrt(sd / n)) if n else 0.0}
+
+
+@contextlib.contextmanager
+def oracle_progress(capsys, every=100):
+    """Let the oracle's own progress lines (one per ``every`` steps of a long
+    run) reach the terminal past pytest's output capture."""
+    oracle.set_progress(every)
+    try:
+        with capsys.disabled():
+            yield
+    finally:
+        oracle.set_progress(0)

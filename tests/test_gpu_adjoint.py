@@ -18,7 +18,7 @@ import torch
 
 import oracle
 import synth
-from tests.gpu_util import errors
+from tests.gpu_util import errors, oracle_progress
 
 pytestmark = pytest.mark.gpu
 
@@ -233,7 +233,7 @@ def test_c3_forward_traces_vs_oracle(gpu_lib, c3):
     assert e["rel_l2"] <= 3e-4
 
 
-def test_c3_gradient_vs_checkpointed_oracle(gpu_lib, c3):
+def test_c3_gradient_vs_checkpointed_oracle(gpu_lib, c3, capsys):
     # The oracle's gradient and its residual r = R u - d (FP64).  The GPU
     # adjoint is driven by that same residual (rounded to FP32), so both
     # adjoints take identical inputs and the comparison measures the GPU's
@@ -243,8 +243,9 @@ def test_c3_gradient_vs_checkpointed_oracle(gpu_lib, c3):
     # the near-source receivers make small (reported, bounded loosely).
     from paper_2309_04671_amd.adjoint import WaveOp, misfit_gradient
     co, v0, dt, dx = c3["co"], c3["v0"], c3["dt"], c3["dx"]
-    J_ref, g_ref, tr_ref = oracle.adjoint_grad_ckpt(co, v0, dt, dx, C3_NT, c3["src"], c3["amp"],
-                                                    c3["rec"], c3["obs"], C3_CKPT, traces=True)
+    with oracle_progress(capsys, 100):
+        J_ref, g_ref, tr_ref = oracle.adjoint_grad_ckpt(co, v0, dt, dx, C3_NT, c3["src"], c3["amp"],
+                                                        c3["rec"], c3["obs"], C3_CKPT, traces=True)
     res_ref = tr_ref - c3["obs"]
     prob = _problem(co, v0, dt, dx, C3_NT, c3["src"], c3["amp"], c3["rec"], ckpt=C3_CKPT)
     vt = torch.tensor(v0, device="cuda")

@@ -22,20 +22,14 @@ import torch
 
 import oracle
 import synth
-from tests.gpu_util import errors
+from tests.gpu_util import errors, oracle_progress
 
 pytestmark = pytest.mark.gpu
 
 BARS = {"fp32": (2e-4, 1e-6), "fp16_store": (4e-2, 1e-2), "bf16_store": (1.0, 0.2)}
 
 
-def _storage_errors(n, nt=1000, n_e=400):
-    from paper_2309_04671_amd import fields, lib
-    vel = synth.layered_velocity(n, n, n, 0)
-    dx = 10.0
-    dt = synth.cfl_dt(vel, dx)
-    amp32 = synth.ricker(nt, dt, 15.0)[:, None].astype(np.float32)
-    src = np.array([[n // 2, n // 2, n // 2]], np.int32)
+def _oracle_run(nt, vel, dt, dx, src, amp32):
     co_d = synth.star25_coeffs()
     st = None
     for k0 in range(0, nt, 100):
@@ -43,8 +37,22 @@ def _storage_errors(n, nt=1000, n_e=400):
         st = oracle.wave_run(co_d, vel, dt, dx, k1 - k0, src=src, amp=amp32[k0:k1].astype(np.float64),
                              prev=None if st is None else st["prev"],
                              cur=None if st is None else st["cur"])
-    ref = oracle.interior(st["cur"]).copy()
-    del st
+    return oracle.interior(st["cur"]).copy()
+
+
+def _storage_errors(n, nt=1000, n_e=400, capsys=None):
+    from paper_2309_04671_amd import fields, lib
+    vel = synth.layered_velocity(n, n, n, 0)
+    dx = 10.0
+    dt = synth.cfl_dt(vel, dx)
+    amp32 = synth.ricker(nt, dt, 15.0)[:, None].astype(np.float32)
+    src = np.array([[n // 2, n // 2, n // 2]], np.int32)
+    co_d = synth.star25_coeffs()
+    if capsys is None:
+        ref = _oracle_run(nt, vel, dt, dx, src, amp32)
+    else:
+        with oracle_progress(capsys, 100):
+            ref = _oracle_run(nt, vel, dt, dx, src, amp32)
 
     gv = lib.grid_init(n, n, n, lib.SP_F32)
     V = fields.Field(gv).set_interior(vel)
@@ -77,8 +85,8 @@ def _storage_errors(n, nt=1000, n_e=400):
     return out
 
 
-def _check(n):
-    res = _storage_errors(n)
+def _check(n, capsys=None):
+    res = _storage_errors(n, capsys=capsys)
     for name, e in res.items():
         print("%d^3 %-10s rel-L2 %.2e  max abs %.2e  RMSD %.2e  (peak %.3f)  energy drift %+.1e"
               % (n, name, e["rel_l2"], e["max_abs"], e["rmsd"], e["ref_max"], e["energy_drift"]))
@@ -93,5 +101,5 @@ def test_storage_forms_vs_oracle_128(gpu_lib):
     _check(128)
 
 
-def test_storage_forms_vs_oracle_512(gpu_lib):
-    _check(512)
+def test_storage_forms_vs_oracle_512(gpu_lib, capsys):
+    _check(512, capsys)
