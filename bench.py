@@ -302,14 +302,93 @@ def leg_storage_vs_fp32(torch, lib, fields, synth, n=512, nt=1000, n_e=400):
     return out
 
 
+def oracle_cores():
+    import oracle
+    return oracle.num_threads()
+
+
+def leg_storage_vs_oracle(torch, lib, fields, synth, n=128, nt=1000):
+    """The three storage forms against the FP64 oracle after nt steps of the
+    n^3 storage workload (same model, source and wavelet as the 512^3 legs):
+    rel-L2, max abs and RMSD of the final field.  The oracle run is timed on
+    the host cores (it is this leg's CPU baseline)."""
+    import numpy as np
+    import oracle
+    vel = synth.layered_velocity(n, n, n, 0)
+    dx = 10.0
+    dt = synth.cfl_dt(vel, dx)
+    amp32 = synth.ricker(nt, dt, 15.0)[:, None].astype(np.float32)
+    src_xyz = np.array([[n // 2, n // 2, n // 2]], np.int32)
+    co_d = synth.star25_coeffs()
+    t0 = time.perf_counter()
+    r = oracle.wave_run(co_d, vel, dt, dx, nt, src=src_xyz, amp=amp32.astype(np.float64))
+    t_or = time.perf_counter() - t0
+    ref = oracle.interior(r["cur"]).copy()
+    del r
+    gv = lib.grid_init(n, n, n, lib.SP_F32)
+    V = fields.Field(gv).set_interior(vel)
+    amp = torch.tensor(amp32, device="cuda")
+    src = lib.make_sources(src_xyz, amp.data_ptr(), 1)
+    co = lib.coeffs(co_d)
+    nref = float(np.linalg.norm(ref))
+    out = {"config": "%d^3, %d steps, layered v seed 0, Ricker 15 Hz at centre; final field "
+                     "against the FP64 oracle" % (n, nt),
+           "peak": float(np.max(np.abs(ref))),
+           "oracle": {"value": round(n ** 3 * nt / t_or / 1e9, 4), "unit": "GPts/s",
+                      "seconds": round(t_or, 2), "cores": oracle_cores(), "kind": "oracle",
+                      "sample": "the whole %d^3 x %d-step run" % (n, nt)}}
+    for name, dtype in (("fp32", lib.SP_F32), ("fp16_store", lib.SP_F16), ("bf16_store", lib.SP_BF16)):
+        g = lib.grid_init(n, n, n, dtype)
+        ws = fields.WaveState(g)
+        lib.sp_wave_step(g, co, dt, dx, gv, V.ptr, ws.st, nt, src=src)
+        torch.cuda.synchronize()
+        d = ws.decoded().astype(np.float64) - ref
+        out[name] = {"rel_l2_vs_oracle": float(np.linalg.norm(d) / nref),
+                     "max_abs_vs_oracle": float(np.max(np.abs(d))),
+                     "rmsd_vs_oracle": float(np.sqrt(np.mean(d * d)))}
+        del ws, d
+    return out
+
+
+def oracle_c0_and_adjoint(synth):
+    """The oracle beside the two small forms: one 25-point sweep at 64^3 (C0)
+    and the misfit gradient at 48^3 x 200 steps (the gradient check's size),
+    timed on the host cores."""
+    import numpy as np
+    import oracle
+    u = oracle.padded(synth.uniform_field((64, 64, 64), 0))
+    co = synth.star25_coeffs()
+    reps = 0
+    t0 = time.perf_counter()
+    while reps < 20 or time.perf_counter() - t0 < 1.0:
+        oracle.laplacian(u, co)
+        reps += 1
+    t_c0 = (time.perf_counter() - t0) / reps
+    n, nt = 48, 200
+    v = synth.gaussian_bump(synth.layered_velocity(n, n, n, 0), (24, 24, 24), 4.0, 0.10)
+    dx = 10.0
+    dt = synth.cfl_dt(v, dx)
+    src = np.array([[24, 24, 8]], np.int32)
+    rec = synth.receiver_plane(n, n, n - 8, 2)
+    amp = synth.ricker(nt, dt, 15.0)[:, None]
+    obs = np.zeros((nt, len(rec)))
+    t0 = time.perf_counter()
+    oracle.adjoint_grad(co, v, dt, dx, nt, src, amp, rec, obs)
+    t_adj = time.perf_counter() - t0
+    cores = oracle_cores()
+    return ({"value": round(64 ** 3 / t_c0 / 1e9, 4), "unit": "GPts/s", "us_per_sweep": round(t_c0 * 1e6, 1),
+             "cores": cores, "kind": "oracle", "sample": "%d sweeps of 64^3" % reps},
+            {"value": round(n ** 3 * nt / t_adj / 1e9, 4), "unit": "GPts/s (time steps of the gradient)",
+             "seconds": round(t_adj, 2), "cores": cores, "kind": "oracle",
+             "sample": "misfit gradient at %d^3 x %d steps, every state kept" % (n, nt)})
+
+
 def leg_adjoint(torch, lib, fields, synth, n=256, nt=1000, ckpt=32):
     """Misfit gradient at n^3 x nt (checkpoint every ckpt steps): wall time of
     forward + backward against the plain forward run."""
     import numpy as np
     from paper_2309_04671_amd.adjoint import WaveOp, WaveProblem
-    v = synth.layered_velocity(n, n, n, 0)
-    v0 = synth.gaussian_bump(v, (n // 2, n // 2, n // 2), 10.0, 0.10)
-    v_obs = synth.gaussian_bump(v0, (96 * n // 256, 160 * n // 256, 160 * n // 256), 12.0, 0.05)
+    v0, v_obs = synth.adjoint_models(n)
     dx = 10.0
     dt = synth.cfl_dt(v0, dx)
     src = np.array([[n // 2, n // 2, 8]], np.int32)
@@ -499,7 +578,7 @@ def leg_serve(torch, lib, fields, synth, nreq=96, loads=(0.5, 0.8, 1.0), budget_
     top-level figures are those at load 0.8; `loads` holds all three."""
     import numpy as np
     from paper_2309_04671_amd import serve
-    budget = int(budget_gb * (1 << 30))
+    budget = int(budget_gb * 1e9)
     arena = budget + (256 << 20)
     cl = serve.ServeClient(arena_bytes=arena, budget_bytes=budget, max_slots=slots, chunk_steps=chunk)
     # capacity: a saturating batch submitted at once
@@ -593,7 +672,7 @@ def main():
                     help="override the headline grid (profiling runs only)")
     ap.add_argument("--no-headline", action="store_true",
                     help="skip the headline run (profiling runs of the extra legs)")
-    ap.add_argument("--legs", default="storage,storage_error,adjoint,fused,pml,suite,serve",
+    ap.add_argument("--legs", default="storage,storage_error,storage_oracle,adjoint,fused,pml,suite,serve",
                     help="extra measurements after the headline run (comma list; '' for none)")
     ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
                     help="instead of the benchmark, copy a GIB-sized buffer 4 times with torch "
@@ -709,7 +788,7 @@ def main():
                      "traffic": traffic,
                      "avg_launch_us": round(launch_s * 1e6, 2) if ev else None,
                      "bytes_per_launch": bpp * npts},
-        "hbm_frac_of_wall": round(gpts * BYTES_PER_POINT / HBM_PEAK_GBS, 4),
+        "hbm_frac_of_wall": round(gpts * bpp / HBM_PEAK_GBS, 4),
         "gflops": round(gpts * FLOPS_PER_POINT, 1),
     }
     del ws, V
@@ -722,6 +801,10 @@ def main():
     if "storage_error" in legs:
         log("storage forms against FP32 at 512^3")
         forms["storage_vs_fp32_512"] = leg_storage_vs_fp32(torch, lib, fields, synth)
+        torch.cuda.empty_cache()
+    if "storage_oracle" in legs:
+        log("storage forms against the FP64 oracle at 128^3")
+        forms["storage_vs_oracle_128"] = leg_storage_vs_oracle(torch, lib, fields, synth)
         torch.cuda.empty_cache()
     if "adjoint" in legs:
         log("adjoint gradient at 256^3")
@@ -749,6 +832,12 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline()
+        if forms:
+            c0, adj = oracle_c0_and_adjoint(synth)
+            if "suite" in forms or "apply" in forms:
+                forms["suite" if "suite" in forms else "apply"]["apply25_64^3_latency"]["oracle"] = c0
+            if "adjoint_256" in forms:
+                forms["adjoint_256"]["oracle_48"] = adj
     print(json.dumps(out), flush=True)
 
 

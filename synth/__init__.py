@@ -91,6 +91,20 @@ def gaussian_bump(v: np.ndarray, center, sigma: float, frac: float) -> np.ndarra
             ).astype(np.float32)
 
 
+def adjoint_models(n: int, seed: int = 0):
+    """Velocity models of the n^3 misfit-gradient workload: the model v0 is
+    the layered model (seed) with a 10 % Gaussian anomaly at (n/2, n/2,
+    3n/16), sigma 10n/256 cells; the data come from v_obs, v0 with a further
+    5 % Gaussian at (3n/8, 5n/8, n/4), sigma 12n/256.  Both anomalies lie
+    within the depth whose reflections reach the receiver plane z = 8 within
+    1000 steps at n = 256 (two-way vertical time about 0.28 s and 0.42 s of
+    the 0.92 s simulated).  Returns (v0, v_obs), FP32 (nz, ny, nx)."""
+    v = layered_velocity(n, n, n, seed)
+    v0 = gaussian_bump(v, (n // 2, n // 2, 3 * n // 16), 10.0 * n / 256, 0.10)
+    v_obs = gaussian_bump(v0, (3 * n // 8, 5 * n // 8, n // 4), 12.0 * n / 256, 0.05)
+    return v0, v_obs
+
+
 def cfl_dt(v: np.ndarray, dx: float, cfl: float = 0.4) -> float:
     """Time step at a given Courant number: dt = cfl * dx / max(v) (FP64)."""
     return cfl * dx / float(np.max(v))

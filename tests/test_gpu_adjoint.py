@@ -192,8 +192,9 @@ def test_energy_matches_oracle_and_is_conserved(gpu_lib):
 
 # ---------------------------------------------------------------------------
 # The adjoint workload at full size: 256^3, layered model plus a 10 %
-# Gaussian anomaly at the centre (sigma 10), data from the same model with a
-# 5 % anomaly at (96, 160, 160) (sigma 12), Ricker 15 Hz at (128, 128, 8),
+# Gaussian anomaly at (128, 128, 48) (sigma 10), data from the same model
+# with a further 5 % anomaly at (96, 160, 64) (sigma 12), both within reach
+# of the recording (synth.adjoint_models), Ricker 15 Hz at (128, 128, 8),
 # 16384 receivers on the plane z = 8 (every second cell), 1000 steps, a
 # checkpoint every 32 steps.  The expected values come from the oracle's
 # checkpointed FP64 adjoint.
@@ -204,9 +205,7 @@ C3_N, C3_NT, C3_CKPT = 256, 1000, 32
 @pytest.fixture(scope="module")
 def c3():
     n, nt = C3_N, C3_NT
-    v = synth.layered_velocity(n, n, n, 0)
-    v0 = synth.gaussian_bump(v, (n // 2, n // 2, n // 2), 10.0, 0.10)
-    v_obs = synth.gaussian_bump(v0, (96, 160, 160), 12.0, 0.05)
+    v0, v_obs = synth.adjoint_models(n)
     dx = 10.0
     dt = synth.cfl_dt(v0, dx)
     src = np.array([[n // 2, n // 2, 8]], np.int32)
