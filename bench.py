@@ -351,9 +351,11 @@ def leg_storage_vs_oracle(torch, lib, fields, synth, n=128, nt=1000):
 
 
 def oracle_c0_and_adjoint(synth):
-    """The oracle beside the two small forms: one 25-point sweep at 64^3 (C0)
-    and the misfit gradient at 48^3 x 200 steps (the gradient check's size),
-    timed on the host cores."""
+    """The oracle beside the small forms, timed on the host cores: one
+    25-point sweep at 64^3 (C0), the misfit gradient at 48^3 x 200 steps
+    (the gradient check's size), and bounded samples of the full-size ones:
+    the checkpointed gradient at 256^3 over 24 steps (the adjoint workload's
+    grid) and 10 leapfrog steps at 512^3 (the storage forms' grid)."""
     import numpy as np
     import oracle
     u = oracle.padded(synth.uniform_field((64, 64, 64), 0))
@@ -375,12 +377,39 @@ def oracle_c0_and_adjoint(synth):
     t0 = time.perf_counter()
     oracle.adjoint_grad(co, v, dt, dx, nt, src, amp, rec, obs)
     t_adj = time.perf_counter() - t0
+    # the 256^3 adjoint workload, 24 steps with a checkpoint every 6
+    n3, nt3, c3 = 256, 24, 6
+    v0, _ = synth.adjoint_models(n3)
+    dt3 = synth.cfl_dt(v0, dx)
+    src3 = np.array([[n3 // 2, n3 // 2, 8]], np.int32)
+    rec3 = synth.receiver_plane(n3, n3, 8, 2)
+    amp3 = synth.ricker(nt3, dt3, 15.0)[:, None]
+    t0 = time.perf_counter()
+    oracle.adjoint_grad_ckpt(co, v0, dt3, dx, nt3, src3, amp3, rec3, np.zeros((nt3, len(rec3))), c3)
+    t_adj3 = time.perf_counter() - t0
+    del v0
+    # the 512^3 storage workload, 10 FP64 leapfrog steps
+    n5, nt5 = 512, 10
+    v5 = synth.layered_velocity(n5, n5, n5, 0)
+    dt5 = synth.cfl_dt(v5, dx)
+    t0 = time.perf_counter()
+    oracle.wave_run(co, v5, dt5, dx, nt5, src=np.array([[n5 // 2] * 3], np.int32),
+                    amp=synth.ricker(nt5, dt5, 15.0)[:, None])
+    t_5 = time.perf_counter() - t0
+    del v5
     cores = oracle_cores()
     return ({"value": round(64 ** 3 / t_c0 / 1e9, 4), "unit": "GPts/s", "us_per_sweep": round(t_c0 * 1e6, 1),
              "cores": cores, "kind": "oracle", "sample": "%d sweeps of 64^3" % reps},
             {"value": round(n ** 3 * nt / t_adj / 1e9, 4), "unit": "GPts/s (time steps of the gradient)",
              "seconds": round(t_adj, 2), "cores": cores, "kind": "oracle",
-             "sample": "misfit gradient at %d^3 x %d steps, every state kept" % (n, nt)})
+             "sample": "misfit gradient at %d^3 x %d steps, every state kept" % (n, nt)},
+            {"value": round(n3 ** 3 * nt3 / t_adj3 / 1e9, 4), "unit": "GPts/s (time steps of the gradient)",
+             "seconds": round(t_adj3, 2), "cores": cores, "kind": "oracle",
+             "sample": "misfit gradient at %d^3 x %d steps, checkpoint every %d (forward, recompute, "
+                       "adjoint and FP64 sum)" % (n3, nt3, c3)},
+            {"value": round(n5 ** 3 * nt5 / t_5 / 1e9, 4), "unit": "GPts/s",
+             "seconds": round(t_5, 2), "cores": cores, "kind": "oracle",
+             "sample": "%d FP64 leapfrog steps at %d^3" % (nt5, n5)})
 
 
 def leg_adjoint(torch, lib, fields, synth, n=256, nt=1000, ckpt=32):
@@ -423,7 +452,7 @@ def leg_adjoint(torch, lib, fields, synth, n=256, nt=1000, ckpt=32):
     J, g = fwd_bwd()
     torch.cuda.synchronize()
     t_all = time.perf_counter() - t0
-    bytes_per_step = 72      # forward 16 + recompute 16 + adjoint step 16 + gradient 24 (B/pt)
+    bytes_per_step = 68      # forward 16 + recompute 16 + fused adjoint step 36 (B/pt)
     return {"config": "%d^3, %d steps, checkpoint every %d, %d receivers" % (n, nt, ckpt, len(rec)),
             "forward_s": round(t_fwd, 4), "forward_backward_s": round(t_all, 4),
             "first_call_s": round(t_first, 4),
@@ -833,11 +862,14 @@ def main():
         log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline()
         if forms:
-            c0, adj = oracle_c0_and_adjoint(synth)
+            c0, adj, adj256, st512 = oracle_c0_and_adjoint(synth)
             if "suite" in forms or "apply" in forms:
                 forms["suite" if "suite" in forms else "apply"]["apply25_64^3_latency"]["oracle"] = c0
             if "adjoint_256" in forms:
                 forms["adjoint_256"]["oracle_48"] = adj
+                forms["adjoint_256"]["oracle_256"] = adj256
+            if "storage_512" in forms:
+                forms["storage_512"]["oracle"] = st512
     print(json.dumps(out), flush=True)
 
 

@@ -278,6 +278,17 @@ int sp_grad_finish(const sp_grid *gv, const float *v, const double *G, float *ou
                    void *stream);
 
 /*
+ * sp_decode -- the interior of a wavefield as plain FP32 values: out is a
+ * DEVICE FP32 array [nz][ny][nx] (x fastest, no halo) receiving q * s_k for
+ * every interior point of `field` (grid g), where s_k is the slab scale of
+ * field u^k read from slot k mod 4 of `meta` (FP16/BF16; exact, the scales
+ * being powers of two).  For FP32 grids meta and k are ignored and the
+ * values are copied.  out must not overlap the field.
+ */
+int sp_decode(const sp_grid *g, const void *field, const void *meta, int64_t k, float *out,
+              void *stream);
+
+/*
  * sp_energy -- discrete energy of the leapfrog of Eq. 2 (Sec. 2.2) between
  * u0 = u^n and u1 = u^{n+1} (FP32 grids), accumulated in FP64:
  *     E = sum (u1 - u0)^2 / m - sum u1 * (L u0),   m = (v dt / dx)^2,
@@ -355,6 +366,10 @@ int sp_wave_step_pml(const sp_grid *g, const sp_coeffs *c, double dt, double dx,
  * at the next chunk boundary as slots and memory free up.  Each shot
  * computes exactly what sp_wave_step computes for it alone (same kernels,
  * same per-point arithmetic), so its results do not depend on the mix.
+ * A shot whose leapfrog computes an infinity or a NaN at any interior point
+ * (a blown-up run: unstable dt, an infinite amplitude) ends at the close of
+ * that chunk as SP_SHOT_FAILED with error SP_ENUMERIC; its memory returns to
+ * the arena and the other shots run on unaffected.
  * ---------------------------------------------------------------------- */
 
 #define SP_QUEUE_EAGER 1   /* launch chunks directly instead of through captured graphs */
@@ -393,7 +408,7 @@ typedef struct {
 
 typedef struct {
     int32_t state;          /* SP_SHOT_* */
-    int32_t error;          /* SP_* code of a failed shot */
+    int32_t error;          /* SP_* code of a failed shot (SP_ENUMERIC: non-finite values) */
     int64_t steps_done;
     double t_submit, t_admit, t_done;   /* seconds on the host's steady clock */
 } sp_shot_status;

@@ -685,6 +685,37 @@ int sp_wave_adjoint_step(const sp_grid *g, const sp_coeffs *c, double dt, double
     const sp::SrcList fwd_src = a.src;      // forward sources: gradient term only
     hipStream_t s = static_cast<hipStream_t>(stream);
     const float inj_scale = (float)((dt / dx) * (dt / dx));   // m g = dt^2 v^2 g / dx^2
+    // One fused sweep per step (propagation and gradient, two register
+    // queues per thread) plus a receiver kernel, on one-row tiles; the tile
+    // override may name a configuration without it, which then takes three
+    // launches (propagation, receivers, gradient sweep).
+    sp::TileCfg tf;
+    if (!tiles_for(g, &tf, "sp_wave_adjoint_step", sp::MODE_ADJ)) return SP_EINVAL;
+    if (tf.ry == 1 && tf.tx * tf.ty / 4 <= 512) {
+        sp::SweepArgs fa = a;
+        fill_tiling(fa, tf);
+        fa.src = fwd_src;
+        fa.dx2 = (float)(dx * dx);
+        fa.gacc = G + g->origin;
+        for (int i = 0; i < nsteps; ++i) {
+            const int64_t k = adj->step;
+            fa.u = static_cast<float *>(adj->cur) + g->origin;       // nu^{k+1}
+            fa.prev = static_cast<float *>(adj->prev) + g->origin;   // nu^{k+2} -> nu^k
+            fa.out = const_cast<void *>(fa.prev);
+            fa.u2 = static_cast<const float *>(u_hist[i]) + g->origin;
+            if (fa.src.n > 0) fa.src.amp = src->amp + (k - 1) * src->amp_stride;
+            hipError_t err = sp::launch_sweep(sp::MODE_ADJ, SP_F32, tf, fa, s);
+            if (err == hipSuccess && nrec > 0)
+                err = sp::launch_inject_grad(fa, rec->xyz, nrec, rec->traces + (k - 1) * rec->trace_stride,
+                                             inj_scale, s);
+            if (err != hipSuccess)
+                return fail(SP_EDEVICE, "sp_wave_adjoint_step: launch failed at k=%lld: %s",
+                            (long long)k, hipGetErrorString(err));
+            std::swap(adj->cur, adj->prev);
+            adj->step -= 1;
+        }
+        return ok();
+    }
     for (int i = 0; i < nsteps; ++i) {
         const int64_t k = adj->step;
         float *nu1 = static_cast<float *>(adj->cur) + g->origin;    // nu^{k+1}
@@ -727,6 +758,27 @@ int sp_grad_finish(const sp_grid *gv, const float *v, const double *G, float *ou
                                             gv->pitch_x, gv->pitch_x * gv->pitch_y, gv->nx,
                                             gv->ny, gv->nz, static_cast<hipStream_t>(stream));
     if (err != hipSuccess) return fail(SP_EDEVICE, "sp_grad_finish: %s", hipGetErrorString(err));
+    return ok();
+}
+
+int sp_decode(const sp_grid *g, const void *field, const void *meta, int64_t k, float *out,
+              void *stream) {
+    if (int e = check_grid(g, "sp_decode")) return e;
+    if (!field || !out) return fail(SP_EINVAL, "sp_decode: NULL argument");
+    const float *scale = nullptr;
+    if (g->dtype != SP_F32) {
+        if (!meta) return fail(SP_EINVAL, "sp_decode: FP16/BF16 fields need their slab records");
+        const int64_t nslab = (g->nz + SP_SLAB - 1) / SP_SLAB;
+        scale = static_cast<const float *>(meta) + ((k % 4 + 4) % 4) * 2 * nslab;
+    }
+    const int64_t n = (int64_t)g->nx * g->ny * g->nz;
+    const auto f0 = reinterpret_cast<uintptr_t>(field), o0 = reinterpret_cast<uintptr_t>(out);
+    if (o0 < f0 + (uintptr_t)g->bytes && f0 < o0 + (uintptr_t)(n * (int64_t)sizeof(float)))
+        return fail(SP_EINVAL, "sp_decode: out overlaps the field");
+    hipError_t err = sp::launch_unpack(g->dtype, static_cast<const char *>(field) + g->origin * g->elem_bytes,
+                                       scale, out, g->pitch_x, g->pitch_x * g->pitch_y, g->nx, g->ny,
+                                       g->nz, static_cast<hipStream_t>(stream));
+    if (err != hipSuccess) return fail(SP_EDEVICE, "sp_decode: %s", hipGetErrorString(err));
     return ok();
 }
 

@@ -15,6 +15,7 @@ enum Mode : int {
     MODE_GRAD = 2,    // G += w * (L u + dx^2 f e_src)      (FP64 G; w in `prev`)
     MODE_ENERGY = 3,  // partial[block] = sum (w - u)^2 / m - w L u   (FP64; w in `prev`)
     MODE_PML = 4,     // absorbing-layer leapfrog (damping eta, auxiliary psi; FP32)
+    MODE_ADJ = 5,     // out = 2u - prev + m L u and G += out * (L u2 + dx^2 f e_src)  (FP64 G)
 };
 
 // Stencil weights rounded once to FP32 (paper Eq. 3).
@@ -52,6 +53,7 @@ struct SlabMeta {
 // at the interior origin and typed by the storage type of the launch.
 struct SweepArgs {
     const void *u;       // input field
+    const float *u2;     // MODE_ADJ: the forward field whose Laplacian weights the gradient
     const void *prev;    // u^{n-1} (MODE_WAVE; may alias out)
     const float *v;      // velocity at its origin (MODE_WAVE)
     void *out;           // output field
@@ -67,6 +69,7 @@ struct SweepArgs {
     const float *eta;    // MODE_PML: damping (1/s) on v's layout, frame included
     float *psi;          // MODE_PML: auxiliary field on u's layout, updated in place
     float dt, alpha_dt;  // MODE_PML: time step and frequency shift times dt
+    uint32_t *nonfinite; // batched MODE_WAVE: set non-zero when an output value is not finite
     int tiles_x, tiles_y, zchunk, nzc;
 };
 
@@ -111,6 +114,11 @@ hipError_t launch_record(int dtype, const void *u, const float *scale, int64_t s
 hipError_t launch_inject(float *field, int64_t sy, int64_t sz, const float *v, int64_t vsy,
                          int64_t vsz, int nx, int ny, int nz, const int32_t *xyz, int n,
                          const float *amp, float scale, hipStream_t s);
+// The receiver term of one fused adjoint step (after the MODE_ADJ sweep a):
+// for r < n, w = scale * v[x_r]^2 * amp[r]; out[x_r] += w and
+// G[x_r] += w * (L u2 + dx^2 f e_src)[x_r]  (atomic: duplicates add).
+hipError_t launch_inject_grad(const SweepArgs &a, const int32_t *xyz, int n, const float *amp,
+                              float scale, hipStream_t s);
 // out = 2 G / v on the interior (FP32 grid layout for out, v; FP64 G).
 hipError_t launch_grad_finish(const double *G, const float *v, float *out, int64_t sy, int64_t sz,
                               int nx, int ny, int nz, hipStream_t s);

@@ -102,9 +102,11 @@ struct Shot {
     double t_submit = 0, t_admit = 0, t_done = 0;
     char *f0 = nullptr, *f1 = nullptr;   // the two wavefield allocations
     float *v = nullptr, *meta = nullptr;
+    uint32_t *nonfinite = nullptr;       // device flag: a non-finite value was computed
     void *cur = nullptr, *prev = nullptr;
     hipEvent_t ready = nullptr;          // caller's inputs produced
     bool fresh = false;                  // admitted, not yet initialised on the device
+    bool blown = false;                  // the last chunk computed a non-finite value
 };
 
 struct Group {
@@ -128,6 +130,8 @@ struct sp_queue {
     char *pinned = nullptr;              // host staging of the control part
     Arena arena;
     uint64_t fail_ticket = 0;            // test hook: fail this ticket at admission
+    uint64_t nonfinite_ticket = 0;       // test hook (fake executor): this ticket blows up
+    uint32_t *flags_host = nullptr;      // pinned: the active shots' non-finite flags
 
     std::mutex mu;
     std::condition_variable cv, cv_done;
@@ -149,6 +153,8 @@ struct sp_queue {
 
 namespace {
 
+// Two wavefields, v, then the slab records (FP16/BF16) followed by the
+// shot's non-finite flag.
 int64_t shot_bytes(const sp_grid &g, const sp_grid &gv) {
     return 2 * align256(g.bytes) + align256(gv.bytes) + align256(sp_wave_meta_bytes(&g) + 16);
 }
@@ -279,7 +285,11 @@ int rebuild(sp_queue *q, const std::vector<Shot *> &act, int k) {
 
 // Fill the per-step arguments of the next k steps and run them.
 int run_chunk(sp_queue *q, int k) {
-    if (q->fake) return SP_OK;
+    if (q->fake) {
+        for (auto &g : q->groups)
+            for (Shot *m : g.members) m->blown = m->id == q->nonfinite_ticket;
+        return SP_OK;
+    }
     for (auto &g : q->groups) {
         const int nm = (int)g.members.size();
         auto *args = reinterpret_cast<sp::SweepArgs *>(q->pinned + g.off_args);
@@ -293,6 +303,7 @@ int run_chunk(sp_queue *q, int k) {
                 a = s.run;
                 a.v = s.v + s.gv.origin;
                 sp::step_args(a, &s.g, cur, prev, prev, s.meta, n, s.d.src_amp, s.d.nsrc);
+                a.nonfinite = s.nonfinite;
                 sp::RecArgs &r = recs[(int64_t)i * nm + m];
                 r.field = a.out;
                 r.scale = s.meta ? a.meta.s_out : nullptr;
@@ -331,9 +342,21 @@ int run_chunk(sp_queue *q, int k) {
             e = hipGraphLaunch(q->exec, q->stream);
         }
     }
+    // the resident shots' non-finite flags, read back with the chunk
+    int nflag = 0;
+    for (auto &g : q->groups)
+        for (Shot *m : g.members) {
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(q->flags_host + nflag, m->nonfinite, sizeof(uint32_t),
+                                   hipMemcpyDeviceToHost, q->stream);
+            ++nflag;
+        }
     if (e == hipSuccess) e = hipEventRecord(q->chunk_done, q->stream);
     if (e == hipSuccess) e = hipEventSynchronize(q->chunk_done);
     if (e != hipSuccess) return fail(SP_EDEVICE, "queue: chunk failed: %s", hipGetErrorString(e));
+    nflag = 0;
+    for (auto &g : q->groups)
+        for (Shot *m : g.members) m->blown = q->flags_host[nflag++] != 0;
     return SP_OK;
 }
 
@@ -345,6 +368,7 @@ int init_shot(sp_queue *q, Shot &s) {
     if (e == hipSuccess) e = hipMemsetAsync(s.f1, 0, s.g.bytes, q->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s.v, 0, s.gv.bytes, q->stream);
     if (e == hipSuccess && s.meta) e = hipMemsetAsync(s.meta, 0, sp_wave_meta_bytes(&s.g), q->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s.nonfinite, 0, sizeof(uint32_t), q->stream);
     if (e == hipSuccess)
         e = sp::launch_pack(s.d.v, s.v + s.gv.origin, s.gv.pitch_x, s.gv.pitch_x * s.gv.pitch_y,
                             s.gv.nx, s.gv.ny, s.gv.nz, q->stream);
@@ -401,9 +425,9 @@ void worker_main(sp_queue *q) {
                 s.f0 = base;
                 s.f1 = base + align256(s.g.bytes);
                 s.v = reinterpret_cast<float *>(base + 2 * align256(s.g.bytes));
-                s.meta = s.g.dtype == SP_F32 ? nullptr
-                                             : reinterpret_cast<float *>(base + 2 * align256(s.g.bytes) +
-                                                                         align256(s.gv.bytes));
+                char *rec = base + 2 * align256(s.g.bytes) + align256(s.gv.bytes);
+                s.meta = s.g.dtype == SP_F32 ? nullptr : reinterpret_cast<float *>(rec);
+                s.nonfinite = reinterpret_cast<uint32_t *>(rec + sp_wave_meta_bytes(&s.g));
                 s.cur = s.f1;
                 s.prev = s.f0;
                 s.state = SP_SHOT_RUNNING;
@@ -442,7 +466,12 @@ void worker_main(sp_queue *q) {
                 } else {
                     s.step += k;
                     if (k % 2) std::swap(s.cur, s.prev);
-                    if (s.step >= s.d.nsteps) {
+                    if (s.blown) {
+                        // blown up: its neighbours in the batch are unaffected
+                        // (no shot reads another's memory)
+                        s.state = SP_SHOT_FAILED;
+                        s.error = SP_ENUMERIC;
+                    } else if (s.step >= s.d.nsteps) {
                         const int e = finish_shot(q, s);
                         s.state = e ? SP_SHOT_FAILED : SP_SHOT_DONE;
                         s.error = e;
@@ -495,12 +524,18 @@ int sp_queue_create(const sp_queue_cfg *cfg, sp_queue **out) {
     q->arena.reset(q->ctrl_bytes, shot_space);
     q->ctrl_dev = static_cast<char *>(cfg->arena);
     if (const char *e = std::getenv("SP_TEST_FAIL_TICKET")) q->fail_ticket = std::strtoull(e, nullptr, 10);
+    if (const char *e = std::getenv("SP_TEST_NONFINITE_TICKET"))
+        q->nonfinite_ticket = std::strtoull(e, nullptr, 10);
     if (!q->fake) {
         hipError_t e = hipGetDevice(&q->device);
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&q->stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&q->chunk_done, hipEventDisableTiming);
         if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&q->pinned), q->ctrl_bytes, hipHostMallocDefault);
+        if (e == hipSuccess)
+            e = hipHostMalloc(reinterpret_cast<void **>(&q->flags_host),
+                              sizeof(uint32_t) * (size_t)cfg->max_slots, hipHostMallocDefault);
         if (e != hipSuccess) {
+            if (q->pinned) (void)hipHostFree(q->pinned);
             if (q->stream) (void)hipStreamDestroy(q->stream);
             if (q->chunk_done) (void)hipEventDestroy(q->chunk_done);
             delete q;
@@ -614,6 +649,7 @@ int sp_queue_destroy(sp_queue *q) {
         (void)hipEventDestroy(q->chunk_done);
         (void)hipStreamDestroy(q->stream);
         (void)hipHostFree(q->pinned);
+        (void)hipHostFree(q->flags_host);
     }
     delete q;
     return ok();

@@ -101,6 +101,20 @@ template <> struct Io<__bf16> {
     }
 };
 
+// True if any of the first n (1..4) values is an infinity or a NaN.
+__device__ __forceinline__ bool nonfinite4(const f4v r, int n) {
+    bool bad = !__builtin_isfinite(r.x);
+    if (n > 1) bad |= !__builtin_isfinite(r.y);
+    if (n > 2) bad |= !__builtin_isfinite(r.z);
+    if (n > 3) bad |= !__builtin_isfinite(r.w);
+    return bad;
+}
+
+// One atomic OR per wave whose lanes saw a non-finite output.
+__device__ __forceinline__ void report_nonfinite(uint32_t *flag, bool bad) {
+    if (__builtin_amdgcn_ballot_w64(bad) != 0 && (threadIdx.x & 63) == 0) atomicOr(flag, 1u);
+}
+
 // Depth of the halo-chunk register queue: the LDS frame of plane z is
 // fetched at iteration z-5, the iteration at which the tiles that own those
 // rows fetch them as their z-queue head, so the shared lines are read from
@@ -137,17 +151,20 @@ __device__ float slab_scale(const SweepArgs &a, int k) {
     return ldexpf(1.f, e);
 }
 
-// Leapfrog step with FP16 storage.  The register queue and the LDS plane keep
-// the stored half values (two per VGPR) instead of decoded FP32 values, and
-// every tap is one mixed-precision FMA (half operand, FP32 coefficient and
-// accumulator) whose coefficient already carries the slab scale of the
-// tap's plane: scales are powers of two, so coefficient x scale is exact and
-// no separate decode is needed.  Same tiles, halo mapping, slab records and
-// rounding as the generic body; about half the queue and LDS footprint.
-template <int TX, int TY, int RY>
+// Leapfrog step with FP16 or BF16 storage.  The register queue and the LDS
+// plane keep the stored 16-bit values (two per VGPR) instead of decoded FP32
+// values, and every tap multiplies a stored value by an FP32 coefficient
+// that already carries the slab scale of the tap's plane: scales are powers
+// of two, so coefficient x scale is exact and no separate decode multiply is
+// needed.  For FP16 a tap is one mixed-precision FMA (half operand, FP32
+// coefficient and accumulator); a BF16 value widens to FP32 exactly by a
+// 16-bit shift or mask, then one FMA.  Same tiles, halo mapping, slab
+// records and rounding as the generic body; about half the queue and LDS
+// footprint.
+template <int TX, int TY, int RY, typename T, bool NF>
 __device__ __forceinline__ void star25_wave_h(const SweepArgs &a, const int lin) {
-    typedef Io<_Float16> IO;
-    typedef IO::raw raw;
+    typedef Io<T> IO;
+    typedef typename IO::raw raw;
     constexpr int LX = TX / 4;
     constexpr int NT = LX * (TY / RY);
     constexpr int LC = LX + 2;
@@ -171,9 +188,9 @@ __device__ __forceinline__ void star25_wave_h(const SweepArgs &a, const int lin)
     const int x = x0 + 4 * lx;
     const int ybase = y0 + ly * RY;
     const int64_t sz = a.sz;
-    const _Float16 *u = static_cast<const _Float16 *>(a.u);
-    const _Float16 *uprev = static_cast<const _Float16 *>(a.prev);
-    _Float16 *out = static_cast<_Float16 *>(a.out);
+    const T *u = static_cast<const T *>(a.u);
+    const T *uprev = static_cast<const T *>(a.prev);
+    T *out = static_cast<T *>(a.out);
     const int nslab = a.meta.nslab;
 
     if (lin == 0)
@@ -278,6 +295,7 @@ __device__ __forceinline__ void star25_wave_h(const SweepArgs &a, const int lin)
     const StarCoef &c = a.c;
     float s_out = 1.f, inv_out = 1.f;
     float tmax = 0.f;
+    bool bad = false;                     // a non-finite output seen by this lane
 
     for (int z = zb; z < ze; ++z) {
         const int b = z & 1;
@@ -342,7 +360,7 @@ __device__ __forceinline__ void star25_wave_h(const SweepArgs &a, const int lin)
         for (int j = 0; j < RY; ++j) {
             const raw ctr = q[j][4];
             const raw L = lds[b][ly * RY + j + 4][lx], R = lds[b][ly * RY + j + 4][lx + 2];
-            const _Float16 w[12] = {L.x, L.y, L.z, L.w, ctr.x, ctr.y, ctr.z, ctr.w, R.x, R.y, R.z, R.w};
+            const T w[12] = {L.x, L.y, L.z, L.w, ctr.x, ctr.y, ctr.z, ctr.w, R.x, R.y, R.z, R.w};
             f4v acc;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -382,7 +400,8 @@ __device__ __forceinline__ void star25_wave_h(const SweepArgs &a, const int lin)
                 }
             }
             if (st_ok[j]) {
-                _Float16 *o = out + (int64_t)z * sz + own[j];
+                if (NF) bad |= nonfinite4(res, a.nx - x);
+                T *o = out + (int64_t)z * sz + own[j];
                 // the slab maximum is taken on the scaled FP32 values and
                 // rounded once per wave below: rounding to nearest even is
                 // monotone and odd, so max |round(v)| = round(max |v|)
@@ -407,7 +426,7 @@ __device__ __forceinline__ void star25_wave_h(const SweepArgs &a, const int lin)
             float w = tmax;
 #pragma unroll
             for (int off = 32; off >= 1; off >>= 1) w = fmaxf(w, __shfl_xor(w, off, 64));
-            w = (float)(_Float16)w;                 // the stored magnitude
+            w = (float)(T)w;                        // the stored magnitude
             if ((tid & 63) == 0) atomicMax(&a.meta.a_out[z >> 4], __float_as_uint(w * s_out));
             tmax = 0.f;
         }
@@ -426,15 +445,18 @@ __device__ __forceinline__ void star25_wave_h(const SweepArgs &a, const int lin)
             hq[j][HQ - 1] = hn[j];
         }
     }
+    if (NF) report_nonfinite(a.nonfinite, bad);
 }
 
 // One sweep over the block's tile and z-chunk.
 //   TX: tile width in points (4 per lane), TY: tile height in rows,
-//   RY: adjacent rows per thread (register blocking in y), T: storage type.
-template <int TX, int TY, int RY, int MODE, typename T>
+//   RY: adjacent rows per thread (register blocking in y), T: storage type,
+//   NF: the leapfrog reports non-finite outputs through a.nonfinite (the
+//   served batches; the single-grid sweeps compile without the check).
+template <int TX, int TY, int RY, int MODE, typename T, bool NF = false>
 __device__ __forceinline__ void star25_body(const SweepArgs &a, const int lin) {
-    if constexpr (MODE == MODE_WAVE && std::is_same<T, _Float16>::value) {
-        star25_wave_h<TX, TY, RY>(a, lin);
+    if constexpr (MODE == MODE_WAVE && Io<T>::scaled) {
+        star25_wave_h<TX, TY, RY, T, NF>(a, lin);
         return;
     }
     typedef Io<T> IO;
@@ -449,11 +471,19 @@ __device__ __forceinline__ void star25_body(const SweepArgs &a, const int lin) {
     static_assert(TY % RY == 0, "RY must divide TY");
     static_assert(MODE == MODE_WAVE || !IO::scaled, "only the leapfrog step has FP16/BF16 storage");
     static_assert(MODE != MODE_PML || RY == 1, "the absorbing-layer mode runs one row per thread");
-    constexpr bool VW = (MODE == MODE_WAVE || MODE == MODE_ENERGY || MODE == MODE_PML);  // reads v
+    static_assert(MODE != MODE_ADJ || RY == 1, "the fused adjoint mode runs one row per thread");
+    constexpr bool VW = (MODE == MODE_WAVE || MODE == MODE_ENERGY || MODE == MODE_PML ||
+                         MODE == MODE_ADJ);  // reads v
     typedef double d4v __attribute__((ext_vector_type(4)));
     constexpr bool PW = (MODE == MODE_WAVE || MODE == MODE_GRAD || MODE == MODE_ENERGY ||
-                         MODE == MODE_PML);  // reads `prev`
+                         MODE == MODE_PML || MODE == MODE_ADJ);  // reads `prev`
+    constexpr bool GW = (MODE == MODE_GRAD || MODE == MODE_ADJ);   // accumulates FP64 G
+    // MODE_ADJ streams a second stencil field u2 (its own register queue,
+    // LDS plane and halo chunks); the other modes compile these to size 1
+    constexpr bool TWO = (MODE == MODE_ADJ);
+    constexpr int R2 = TWO ? RY : 1;
     __shared__ f4v lds[2][LR][LC];
+    __shared__ f4v lds2[TWO ? 2 : 1][TWO ? LR : 1][TWO ? LC : 1];
 
     const int tix = lin % a.tiles_x;
     const int rest = lin / a.tiles_x;
@@ -568,20 +598,34 @@ __device__ __forceinline__ void star25_body(const SweepArgs &a, const int lin) {
         nq[j] = ld_ok[j] ? IO::ld(u + (int64_t)(zb + 4) * sz + own[j]) : rzero;
     }
     // halo chunks of planes z .. z+HD-1; the FP32 leapfrog, gradient and
-    // energy sweeps on 1024-thread blocks (a 128-VGPR budget) keep depth 1
-    constexpr int HD = (NT > 512 && MODE != MODE_APPLY && std::is_same<T, float>::value) ? 1 : HQ;
+    // energy sweeps on 1024-thread blocks (a 128-VGPR budget) and the fused
+    // adjoint (two fields) keep depth 1
+    constexpr int HD = ((NT > 512 && MODE != MODE_APPLY && std::is_same<T, float>::value) || TWO) ? 1 : HQ;
     raw hq[HPT][HD];
 #pragma unroll
     for (int j = 0; j < HPT; ++j)
 #pragma unroll
         for (int k = 0; k < HD; ++k)
             hq[j][k] = h_ok[j] ? IO::ld(u + (int64_t)(zb + k) * sz + hoff[j]) : rzero;
+    // MODE_ADJ: the same queue, halo chunks and next plane for u2 (FP32)
+    f4v q2[R2][9], nq2[R2], hq2[TWO ? HPT : 1];
+    if constexpr (TWO) {
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                q2[j][i] = ld_ok[j] ? ld4(a.u2 + (int64_t)(zb - 4 + i) * sz + own[j]) : zero;
+            nq2[j] = ld_ok[j] ? ld4(a.u2 + (int64_t)(zb + 4) * sz + own[j]) : zero;
+        }
+#pragma unroll
+        for (int j = 0; j < HPT; ++j) hq2[j] = h_ok[j] ? ld4(a.u2 + (int64_t)zb * sz + hoff[j]) : zero;
+    }
 
     // Single-use streams (u^{n-1}, v) are fetched PF planes ahead: pp/vv hold
     // plane z, pp1/vv1 plane z+1 when PF = 2 (plane zb+1 <= nz lies in the
     // frame).  1024-thread blocks (a 128-VGPR budget) and the FP64 gradient
     // sweep keep PF = 1.
-    constexpr int PF = (NT > 512 || MODE == MODE_GRAD || MODE == MODE_PML) ? 1 : 2;
+    constexpr int PF = (NT > 512 || GW || MODE == MODE_PML) ? 1 : 2;
     raw pp[RY], pp1[RY];
     f4v vv[RY], vv1[RY];
 #pragma unroll
@@ -603,7 +647,7 @@ __device__ __forceinline__ void star25_body(const SweepArgs &a, const int lin) {
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
         gg[j] = d4v{0.0, 0.0, 0.0, 0.0};
-        if (MODE == MODE_GRAD && st_ok[j])
+        if (GW && st_ok[j])
             gg[j] = *reinterpret_cast<const d4v *>(a.gacc + (int64_t)zb * sz + own[j]);
     }
     double esum = 0.0;                    // MODE_ENERGY: this thread's partial sum
@@ -637,6 +681,7 @@ __device__ __forceinline__ void star25_body(const SweepArgs &a, const int lin) {
     const StarCoef &c = a.c;
     float s_out = 1.f, inv_out = 1.f;     // output scale of the current slab
     float tmax = 0.f;                     // running max |stored output| in the slab
+    bool bad = false;                     // MODE_WAVE: a non-finite output seen by this lane
 
     for (int z = zb; z < ze; ++z) {
         const int b = z & 1;
@@ -655,10 +700,23 @@ __device__ __forceinline__ void star25_body(const SweepArgs &a, const int lin) {
 #pragma unroll
         for (int j = 0; j < HPT; ++j)
             if (tid + j * NT < HC) lds[b][hrow[j]][hchk[j]] = IO::dec(hq[j][0], s0);
+        if constexpr (TWO) {
+#pragma unroll
+            for (int j = 0; j < RY; ++j) {
+                q2[j][8] = nq2[j];
+                lds2[b][ly * RY + j + 4][lx + 1] = q2[j][4];
+            }
+#pragma unroll
+            for (int j = 0; j < HPT; ++j)
+                if (tid + j * NT < HC) lds2[b][hrow[j]][hchk[j]] = hq2[j];
+        }
 
         raw hn[HPT];
+        f4v hn2[TWO ? HPT : 1];
 #pragma unroll
         for (int j = 0; j < HPT; ++j) hn[j] = rzero;
+#pragma unroll
+        for (int j = 0; j < (TWO ? HPT : 1); ++j) hn2[j] = zero;
         raw pp_n[RY];
         f4v vv_n[RY];
         d4v gg_n[RY];
@@ -680,10 +738,18 @@ __device__ __forceinline__ void star25_body(const SweepArgs &a, const int lin) {
                 if (st_ok[j]) {
                     if (PW) pp_n[j] = IO::ld_nt(uprev + (int64_t)(z + PF) * sz + own[j]);
                     if (VW) vv_n[j] = ld4_nt(a.v + (int64_t)(z + PF) * a.vsz + vown[j]);
-                    if (MODE == MODE_GRAD)
+                    if (GW)
                         gg_n[j] = __builtin_nontemporal_load(
                             reinterpret_cast<const d4v *>(a.gacc + (int64_t)(z + 1) * sz + own[j]));
                 }
+            if constexpr (TWO) {
+#pragma unroll
+                for (int j = 0; j < RY; ++j)
+                    nq2[j] = ld_ok[j] ? ld4(a.u2 + (int64_t)(z + 5) * sz + own[j]) : zero;
+#pragma unroll
+                for (int j = 0; j < HPT; ++j)
+                    hn2[j] = h_ok[j] ? ld4(a.u2 + (int64_t)(z + 1) * sz + hoff[j]) : zero;
+            }
         }
         f4v eq_n, ex_n[4], ps_n;
         if constexpr (MODE == MODE_PML) {
@@ -725,7 +791,51 @@ __device__ __forceinline__ void star25_body(const SweepArgs &a, const int lin) {
             }
 
             f4v res;
-            if (MODE == MODE_WAVE) {
+            if constexpr (MODE == MODE_ADJ) {
+                // nu^k = 2 nu^{k+1} - nu^{k+2} + m L nu^{k+1} (the receiver term
+                // follows in a separate kernel); G += nu^k (L u2 + dx^2 f e_src)
+                const f4v m = vv[j] * vv[j] * a.m_scale;
+                res = m * acc + (2.f * ctr - IO::dec(pp[j], 1.f));
+                const f4v c2 = q2[j][4];
+                f4v term = c.c0 * c2;
+#pragma unroll
+                for (int r = 1; r <= 4; ++r) term += c.cz[r - 1] * (q2[j][4 + r] + q2[j][4 - r]);
+                const int row = ly * RY + j + 4;
+#pragma unroll
+                for (int r = 1; r <= 4; ++r)
+                    term += c.cy[r - 1] * (lds2[b][row + r][lx + 1] + lds2[b][row - r][lx + 1]);
+                {
+                    const f4v L = lds2[b][row][lx], R = lds2[b][row][lx + 2];
+                    const float w[12] = {L.x, L.y, L.z, L.w, c2.x, c2.y, c2.z, c2.w, R.x, R.y, R.z, R.w};
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        float o = term[i];
+#pragma unroll
+                        for (int r = 1; r <= 4; ++r) o = fmaf(c.cx[r - 1], w[4 + i + r] + w[4 + i - r], o);
+                        term[i] = o;
+                    }
+                }
+                const int y = ybase + j;
+                for (int s = 0; s < a.src.n; ++s) {
+                    if (a.src.z[s] == z && a.src.y[s] == y) {
+                        const int d = a.src.x[s] - x;
+                        if (d >= 0 && d < 4) term[d] += a.dx2 * s_amp[s];
+                    }
+                }
+                if (st_ok[j]) {
+                    d4v gnew = gg[j];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) gnew[i] = fma((double)res[i], (double)term[i], gnew[i]);
+                    double *go = a.gacc + (int64_t)z * sz + own[j];
+                    if (x + 4 <= a.nx) {
+                        __builtin_nontemporal_store(gnew, reinterpret_cast<d4v *>(go));
+                    } else {
+                        go[0] = gnew[0];
+                        if (x + 1 < a.nx) go[1] = gnew[1];
+                        if (x + 2 < a.nx) go[2] = gnew[2];
+                    }
+                }
+            } else if (MODE == MODE_WAVE) {
                 const f4v m = vv[j] * vv[j] * a.m_scale;
                 res = m * acc + (2.f * ctr - IO::dec(pp[j], sp0));
                 const int y = ybase + j;
@@ -824,6 +934,7 @@ __device__ __forceinline__ void star25_body(const SweepArgs &a, const int lin) {
             }
 
             if (st_ok[j]) {
+                if (MODE == MODE_WAVE && NF) bad |= nonfinite4(res, a.nx - x);
                 T *o = out + (int64_t)z * sz + own[j];
                 const raw enc = IO::enc(res, inv_out);
                 if constexpr (IO::scaled) {
@@ -869,6 +980,14 @@ __device__ __forceinline__ void star25_body(const SweepArgs &a, const int lin) {
             }
             gg[j] = gg_n[j];
         }
+        if constexpr (TWO) {
+#pragma unroll
+            for (int j = 0; j < RY; ++j)
+#pragma unroll
+                for (int i = 0; i < 8; ++i) q2[j][i] = q2[j][i + 1];
+#pragma unroll
+            for (int j = 0; j < HPT; ++j) hq2[j] = hn2[j];
+        }
         if constexpr (MODE == MODE_PML) {
             eq[0] = eq[1];
             eq[1] = eq[2];
@@ -884,6 +1003,8 @@ __device__ __forceinline__ void star25_body(const SweepArgs &a, const int lin) {
             hq[j][HD - 1] = hn[j];
         }
     }
+
+    if constexpr (MODE == MODE_WAVE && NF) report_nonfinite(a.nonfinite, bad);
 
     if constexpr (MODE == MODE_ENERGY) {
         // block sum in a fixed order: waves by shuffles, then wave 0 over LDS
@@ -932,7 +1053,7 @@ template <int TX, int TY, int RY, int MODE, typename T>
 __global__ void __launch_bounds__((TX / 4) * (TY / RY))
 k_star25_batch(const SweepArgs *__restrict__ args, const int2 *__restrict__ table) {
     const int2 e = table[blockIdx.x];
-    star25_body<TX, TY, RY, MODE, T>(args[e.x], e.y);
+    star25_body<TX, TY, RY, MODE, T, true>(args[e.x], e.y);
 }
 
 __global__ void k_inject(float *field, int64_t sy, int64_t sz, const float *v, int64_t vsy,
@@ -944,6 +1065,33 @@ __global__ void k_inject(float *field, int64_t sy, int64_t sz, const float *v, i
     if (x < 0 || x >= nx || y < 0 || y >= ny || z < 0 || z >= nz) return;
     const float vs = v[(int64_t)z * vsz + (int64_t)y * vsy + x];
     atomicAdd(field + (int64_t)z * sz + (int64_t)y * sy + x, scale * (vs * vs) * amp[r]);
+}
+
+// The receiver term of a fused adjoint step: the MODE_ADJ sweep wrote nu^k
+// without it and added nu^k (L u2 + dx^2 f) to G, so each receiver adds
+// its injection w to nu^k and w (L u2 + dx^2 f) to G at its point.
+__global__ void k_inject_grad(const SweepArgs a, const int32_t *xyz, int n, const float *amp,
+                              float scale) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int x = xyz[3 * r], y = xyz[3 * r + 1], z = xyz[3 * r + 2];
+    if (x < 0 || x >= a.nx || y < 0 || y >= a.ny || z < 0 || z >= a.nz) return;
+    const float vs = a.v[(int64_t)z * a.vsz + (int64_t)y * a.vsy + x];
+    const float w = scale * (vs * vs) * amp[r];
+    const int64_t o = (int64_t)z * a.sz + (int64_t)y * a.sy + x;
+    atomicAdd(static_cast<float *>(a.out) + o, w);
+    const float *p = a.u2 + o;
+    const StarCoef &c = a.c;
+    float t = c.c0 * p[0];
+#pragma unroll
+    for (int k = 1; k <= 4; ++k) {
+        t += c.cz[k - 1] * (p[k * a.sz] + p[-k * a.sz]);
+        t += c.cy[k - 1] * (p[k * a.sy] + p[-k * a.sy]);
+        t += c.cx[k - 1] * (p[k] + p[-k]);
+    }
+    for (int s = 0; s < a.src.n; ++s)
+        if (a.src.x[s] == x && a.src.y[s] == y && a.src.z[s] == z) t += a.dx2 * a.src.amp[s];
+    atomicAdd(a.gacc + o, (double)w * (double)t);
 }
 
 __global__ void k_grad_finish(const double *G, const float *v, float *out, int64_t sy, int64_t sz,
@@ -1056,6 +1204,13 @@ hipError_t launch_t(int mode, const SweepArgs &a, hipStream_t s) {
                 hipLaunchKernelGGL((k_star25<TX, TY, RY, MODE_APPLY, T>), grid, block, 0, s, a);
             else if (mode == MODE_GRAD)
                 hipLaunchKernelGGL((k_star25<TX, TY, RY, MODE_GRAD, T>), grid, block, 0, s, a);
+            else if (mode == MODE_ADJ) {
+                // one row per thread, at most 512 threads (two queues per thread)
+                if constexpr (RY == 1 && TX * TY / 4 <= 512)
+                    hipLaunchKernelGGL((k_star25<TX, TY, RY, MODE_ADJ, T>), grid, block, 0, s, a);
+                else
+                    return hipErrorInvalidValue;
+            }
             else if (mode == MODE_ENERGY)
                 hipLaunchKernelGGL((k_star25<TX, TY, RY, MODE_ENERGY, T>), grid, block, 0, s, a);
             else
@@ -1128,12 +1283,11 @@ TileCfg choose_tiles(int nx, int ny, int nz, int dtype, int mode) {
     //  * FP32 (184 VGPRs, 16-byte accesses): 512-thread 256x16x2 tiles, one
     //    block per CU, z split only when there are fewer than 256 tiles
     //    (the leapfrog on grids that need 16-plane chunks: 256x16x1);
-    //  * FP16 (about 150 VGPRs, 8-byte accesses, latency-bound): 256-thread
-    //    tiles, three resident per CU, and many short z-chunks (about 4096
-    //    blocks) so that the CUs stay evenly loaded;
-    //  * BF16 (about 107 VGPRs with one row per thread): 1024-thread
-    //    256x16x1 tiles at four waves per SIMD (about 512 blocks) where the
-    //    grid has at least two of them across x, else the FP16 choice;
+    //  * FP16 and BF16 (the raw 16-bit body: about 165 and 181 VGPRs,
+    //    8-byte accesses, latency-bound): 256-thread 128x16x2 tiles and many
+    //    short z-chunks (about 4096 blocks) so that the CUs stay evenly
+    //    loaded (BF16 at 512^3: 453 GPts/s against 345 on the 1024-thread
+    //    256x16x1 tiles the decoding body had used);
     //  * the FP32 APPLY sweep (8 B per point) runs best on 128x32x2 tiles
     //    with about 256 blocks (one long z-chunk per tile at 1024^2),
     //    measured on live data: constant or overflowed fields run the same
@@ -1141,6 +1295,9 @@ TileCfg choose_tiles(int nx, int ny, int nz, int dtype, int mode) {
     //  * the absorbing-layer mode runs one row per thread in 512-thread
     //    256x8x1 tiles, 64x16x1 or 32x32x1 for narrow boxes (the x slabs),
     //    with the FP32 rule for the z-split;
+    //  * the fused adjoint sweep (two stencil fields per thread) runs one
+    //    row per thread in 512-thread 256x8x1 tiles, 64x16x1 for narrow
+    //    grids, with the FP32 rule for the z-split;
     // z-chunks are at least 16 planes (each chunk re-reads 8 planes of u,
     // mostly from L2).  These targets are measured optima on MI355X.
     struct Cand {
@@ -1148,13 +1305,13 @@ TileCfg choose_tiles(int nx, int ny, int nz, int dtype, int mode) {
     };
     static const Cand c32[3] = {{256, 16, 2, 256, 1}, {128, 16, 2, 512, 1}, {64, 16, 1, 512, 1}};
     static const Cand c16[3] = {{128, 16, 2, 4096, 1}, {128, 16, 2, 4096, 1}, {64, 16, 1, 4096, 1}};
-    static const Cand cbf[3] = {{256, 16, 1, 512, 2}, {128, 16, 2, 4096, 1}, {64, 16, 1, 4096, 1}};
     static const Cand cap[3] = {{128, 32, 2, 256, 1}, {128, 16, 2, 512, 1}, {64, 16, 1, 512, 1}};
     static const Cand cpm[3] = {{256, 8, 1, 256, 1}, {64, 16, 1, 512, 1}, {32, 32, 1, 512, 1}};
-    const Cand *cand = dtype == SP_F16    ? c16
-                       : dtype == SP_BF16 ? cbf
+    static const Cand cad[3] = {{256, 8, 1, 256, 1}, {64, 16, 1, 512, 1}, {64, 16, 1, 512, 1}};
+    const Cand *cand = dtype != SP_F32       ? c16
                        : mode == MODE_APPLY ? cap
                        : mode == MODE_PML   ? cpm
+                       : mode == MODE_ADJ   ? cad
                                             : c32;
     TileCfg t;
     int want = 256;
@@ -1168,7 +1325,7 @@ TileCfg choose_tiles(int nx, int ny, int nz, int dtype, int mode) {
     }
     const int tiles = ((nx + t.tx - 1) / t.tx) * ((ny + t.ty - 1) / t.ty);
     int zc;
-    if (cand == c32 || cand == cpm || cand == cap) {
+    if (cand == c32 || cand == cpm || cand == cap || cand == cad) {
         // FP32 sweeps (leapfrog, gradient, energy, layer, apply): `want`
         // blocks fill the GPU once (one 512-thread or two 256-thread blocks
         // per CU).
@@ -1216,6 +1373,14 @@ hipError_t launch_inject(float *field, int64_t sy, int64_t sz, const float *v, i
     const int bs = 256;
     hipLaunchKernelGGL(k_inject, dim3((n + bs - 1) / bs), dim3(bs), 0, s, field, sy, sz, v, vsy,
                        vsz, nx, ny, nz, xyz, n, amp, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_inject_grad(const SweepArgs &a, const int32_t *xyz, int n, const float *amp,
+                              float scale, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int bs = 256;
+    hipLaunchKernelGGL(k_inject_grad, dim3((n + bs - 1) / bs), dim3(bs), 0, s, a, xyz, n, amp, scale);
     return hipGetLastError();
 }
 

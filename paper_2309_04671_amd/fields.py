@@ -126,12 +126,17 @@ class WaveState:
         self.st.cur, self.st.prev, self.st.step = self.b.ptr, self.a.ptr, 0
         self.spare = [f.ptr for f in self.extra]
 
-    def decoded(self, which="cur") -> np.ndarray:
-        """Interior of u^n (or u^{n-1}) decoded to FP64 with its slab scales."""
+    def decoded_device(self, which="cur") -> torch.Tensor:
+        """Interior of u^n (or u^{n-1}) as FP32 values (nz, ny, nx) on the
+        device, decoded with its slab scales by the library (sp_decode)."""
         f = self.cur() if which == "cur" else self.prev()
-        q = f.get_interior().astype(np.float64)
-        if self.grid.dtype == lib.SP_F32:
-            return q
         k = self.st.step if which == "cur" else self.st.step - 1
-        s = self.slot(k)[0].cpu().numpy().astype(np.float64)
-        return q * s[np.arange(self.grid.nz) // lib.SP_SLAB][:, None, None]
+        g = self.grid
+        out = torch.empty((g.nz, g.ny, g.nx), dtype=torch.float32, device=f.buf.device)
+        meta = self.meta.data_ptr() if g.dtype != lib.SP_F32 else None
+        lib.sp_decode(g, f.ptr, meta, k, out.data_ptr())
+        return out
+
+    def decoded(self, which="cur") -> np.ndarray:
+        """Interior of u^n (or u^{n-1}) decoded with its slab scales, as FP64."""
+        return self.decoded_device(which).cpu().numpy().astype(np.float64)

@@ -25,7 +25,7 @@ ERROR_NAMES = {0: "SP_OK", 1: "SP_EINVAL", 2: "SP_EUNSUPPORTED", 3: "SP_EDEVICE"
 # Every symbol include/stencil.h declares (checked by the ABI tests).
 EXPORTS = [
     "sp_grid_init", "sp_grid_init_2d", "sp_stencil_apply", "sp_apply", "sp_wave_meta_bytes", "sp_wave_step",
-    "sp_wave_step_fused", "sp_wave_run_states", "sp_wave_adjoint_step", "sp_grad_finish", "sp_energy_ws_bytes",
+    "sp_wave_step_fused", "sp_wave_run_states", "sp_wave_adjoint_step", "sp_grad_finish", "sp_decode", "sp_energy_ws_bytes",
     "sp_energy", "sp_pml_profile", "sp_wave_step_pml", "sp_shot_bytes", "sp_queue_create", "sp_submit", "sp_poll", "sp_queue_drain",
     "sp_queue_destroy", "sp_last_error", "sp_version",
 ]
@@ -132,6 +132,7 @@ def load():
                                          P(sp_wave_state), P(vp), i, P(sp_sources),
                                          P(sp_receivers), vp, vp]
     lib.sp_grad_finish.argtypes = [P(sp_grid), vp, vp, vp, vp]
+    lib.sp_decode.argtypes = [P(sp_grid), vp, vp, i64, vp, vp]
     lib.sp_energy_ws_bytes.argtypes = [P(sp_grid)]
     lib.sp_energy_ws_bytes.restype = i64
     lib.sp_energy.argtypes = [P(sp_grid), P(sp_coeffs), d, d, P(sp_grid), vp, vp, vp, vp, vp, vp]
@@ -303,6 +304,11 @@ def sp_wave_adjoint_step(g, c, dt, dx, gv, v_ptr, adj, u_hist, nsteps, src, rec,
 def sp_grad_finish(gv, v_ptr, G_ptr, out_ptr, stream=None):
     check(load().sp_grad_finish(ctypes.byref(gv), ctypes.c_void_p(v_ptr), ctypes.c_void_p(G_ptr),
                                 ctypes.c_void_p(out_ptr), stream_ptr(stream)))
+
+
+def sp_decode(g, field_ptr, meta_ptr, k, out_ptr, stream=None):
+    check(load().sp_decode(ctypes.byref(g), ctypes.c_void_p(field_ptr), ctypes.c_void_p(meta_ptr),
+                           int(k), ctypes.c_void_p(out_ptr), stream_ptr(stream)))
 
 
 def sp_energy(g, c, dt, dx, gv, v_ptr, u0_ptr, u1_ptr, out_ptr, ws_ptr, stream=None):

@@ -28,6 +28,7 @@ pytestmark = pytest.mark.gpu
 TOL_SWEEP = 1e-5
 
 
+@pytest.mark.timeout(600)
 def test_c1_full_field_per_sweep(gpu_lib):
     from paper_2309_04671_amd import fields, lib
     nx, ny, nz, nt = 1024, 1024, 512, 500
@@ -64,6 +65,7 @@ def test_c1_full_field_per_sweep(gpu_lib):
     assert ws.st.step == nt
 
 
+@pytest.mark.timeout(600)
 def test_apply_full_field(gpu_lib):
     from paper_2309_04671_amd import fields, lib
     nx, ny, nz = 1024, 1024, 512
@@ -81,6 +83,7 @@ def test_apply_full_field(gpu_lib):
 
 
 @pytest.mark.parametrize("fmt", ["f16", "bf16"])
+@pytest.mark.timeout(600)
 def test_c2_full_field_single_step(gpu_lib, fmt):
     from paper_2309_04671_amd import fields, lib
     n, n0 = 512, 300

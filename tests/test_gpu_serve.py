@@ -7,7 +7,10 @@ Bars:
  * a queued FP32 shot matches the FP64 oracle (multi-step rel-L2 <= 1e-4);
  * the four served shapes up to 384x384x256, FP32 and FP16 in one mix,
    equal direct runs bit for bit;
- * requests submitted while others run are admitted before those finish.
+ * requests submitted while others run are admitted before those finish;
+ * a shot that blows up (an infinite source amplitude) ends FAILED with
+   SP_ENUMERIC, FP32 or FP16, while its neighbours in the batch finish with
+   the results they have alone.
 """
 
 import time
@@ -142,3 +145,26 @@ def test_c4_shapes_mixed_equal_direct_runs(gpu_lib):
     e = errors(res[0][1], oracle.interior(ref["cur"]))
     print("served 128^3 FP32 shot vs oracle:", e)
     assert e["rel_l2"] <= 1e-4
+
+
+@pytest.mark.parametrize("bad_dtype", [0, 1])
+def test_blown_up_shot_fails_with_enumeric_neighbours_unaffected(gpu_lib, bad_dtype):
+    from paper_2309_04671_amd import lib, serve
+    specs = [(64, 48, 40, 0, 37), (100, 60, 50, 1, 45), (72, 72, 36, bad_dtype, 29)]
+    _, solo = _run(serve, lib, specs[:2], slots=1)
+    cl = serve.ServeClient(arena_bytes=2 << 30, max_slots=8, chunk_steps=8)
+    shots = _shots(serve, lib, specs)
+    bad = shots[2][1]
+    bad.amp[3:] = float("inf")                 # u^4 is infinite at the source
+    for _, s in shots:
+        cl.submit(s)
+    cl.drain()
+    done, st = cl.poll(bad.ticket)
+    assert done and st.state == lib.SP_SHOT_FAILED and st.error == lib.SP_ENUMERIC, (st.state, st.error)
+    assert st.steps_done == 8                  # found at the end of the first chunk
+    for k in range(2):
+        done, st = cl.poll(shots[k][1].ticket)
+        assert done and st.state == lib.SP_SHOT_DONE
+        assert np.array_equal(shots[k][1].traces.cpu().numpy(), solo[k][0]), k
+        assert np.array_equal(shots[k][1].final.cpu().numpy(), solo[k][1]), k
+    cl.close()

@@ -101,5 +101,6 @@ def test_storage_forms_vs_oracle_128(gpu_lib):
     _check(128)
 
 
+@pytest.mark.timeout(600)
 def test_storage_forms_vs_oracle_512(gpu_lib, capsys):
     _check(512, capsys)

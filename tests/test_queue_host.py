@@ -3,7 +3,8 @@ thread admits, batches and retires shots but enqueues no device work).
 
 Checks admission by budget and slots (resident bytes never exceed the
 budget), FIFO order, rejection of shots that can never fit, isolation of a
-failing shot with full arena reclamation, and cancellation at shutdown.
+failing shot and of a shot that computes a non-finite value (SP_ENUMERIC),
+with full arena reclamation, and cancellation at shutdown.
 """
 
 import ctypes
@@ -120,6 +121,30 @@ def test_failing_shot_is_isolated_and_memory_reclaimed(monkeypatch):
         if t != 2:
             assert sts[t][1].state == lib.SP_SHOT_DONE and sts[t][1].steps_done == 30
     # everything was returned: a shot needing the whole budget is admitted
+    big = desc(40, 5)
+    tickets2 = [submit(q, big)[1] for _ in range(3)]
+    lib.check(L.sp_queue_drain(q))
+    assert all(status(q, t)[1].state == lib.SP_SHOT_DONE for t in tickets2)
+    lib.check(L.sp_queue_destroy(q))
+
+
+def test_nonfinite_shot_fails_with_enumeric_and_memory_reclaimed(monkeypatch):
+    # the fake executor reports a non-finite value for ticket 3 after its
+    # first chunk: that shot ends FAILED / SP_ENUMERIC with the steps of
+    # that chunk done, the others finish, and its memory returns
+    L = lib.load()
+    monkeypatch.setenv("SP_TEST_NONFINITE_TICKET", "3")
+    d = desc(40, 30)
+    b = L.sp_shot_bytes(ctypes.byref(d))
+    q = make_queue(1 << 30, budget=3 * b, slots=4, chunk=4)
+    tickets = [submit(q, desc(40, 30))[1] for _ in range(5)]
+    lib.check(L.sp_queue_drain(q))
+    sts = {t: status(q, t) for t in tickets}
+    assert sts[3][0] == lib.SP_OK and sts[3][1].state == lib.SP_SHOT_FAILED
+    assert sts[3][1].error == lib.SP_ENUMERIC and sts[3][1].steps_done == 4
+    for t in tickets:
+        if t != 3:
+            assert sts[t][1].state == lib.SP_SHOT_DONE and sts[t][1].steps_done == 30
     big = desc(40, 5)
     tickets2 = [submit(q, big)[1] for _ in range(3)]
     lib.check(L.sp_queue_drain(q))
