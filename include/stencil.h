@@ -304,6 +304,25 @@ int sp_energy(const sp_grid *g, const sp_coeffs *c, double dt, double dx,
               const sp_grid *gv, const float *v, const void *u0, const void *u1,
               double *out, void *ws, void *stream);
 
+/*
+ * sp_energy_noalloc -- sp_energy without a workspace argument, for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  Same arguments and
+ * result as sp_energy minus ws; calls no allocating routine.  The per-block
+ * partial sums go to a static device array of
+ * sp_energy_noalloc_max_partials() doubles (512 KiB), one per device, held
+ * until the process ends; grids whose sweep needs more partial sums fail
+ * with SP_ENOMEM (use sp_energy).  Every partial is written before it is
+ * read, so nothing carries over from an earlier call.  All calls on one
+ * device share that array: calls that overlap on one device (different
+ * streams, or host threads without ordering) race.  `stream` must belong to
+ * the current device (SP_EINVAL otherwise).
+ */
+int64_t sp_energy_noalloc_max_partials(void);
+int sp_energy_noalloc(const sp_grid *g, const sp_coeffs *c, double dt, double dx,
+                      const sp_grid *gv, const float *v, const void *u0, const void *u1,
+                      double *out, void *stream);
+
 /* ------------------------------------------------------------------------
  * Absorbing layer: the inner and PML regions of Sec. 2.2.
  *

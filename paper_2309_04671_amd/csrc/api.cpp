@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 
 #include "internal.h"
 
@@ -814,6 +815,47 @@ int energy_launch(const char *who, sp::SweepArgs &a, const sp::TileCfg &t, int n
     return ok();
 }
 
+// The allocation-free energy keeps its per-block partial sums in this
+// file-scope device array instead of a caller workspace.  Each device the
+// library runs on holds its own copy until the process ends.  In host code
+// the name `scratch` is only a stand-in for the symbol: its device address
+// is looked up once per device (scratch_for_device) and used instead.
+constexpr int kScratchPartials = 1 << 16;   // 512 KiB of FP64 partial sums
+static __device__ __align__(256) double scratch[kScratchPartials];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices];         // device address of `scratch`, per device
+
+// Device address of the current device's `scratch`; the stream must belong
+// to the current device (the launch and the address must agree).
+int scratch_for_device(const char *who, void *stream, double **out) {
+    int dev = -1;
+    hipError_t err = hipGetDevice(&dev);
+    if (err != hipSuccess) return fail(SP_EDEVICE, "%s: %s", who, hipGetErrorString(err));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(SP_EUNSUPPORTED, "%s: device ordinal %d (max %d)", who, dev, kMaxDevices - 1);
+    if (stream) {
+        hipDevice_t sdev = -1;
+        err = hipStreamGetDevice(static_cast<hipStream_t>(stream), &sdev);
+        if (err != hipSuccess) return fail(SP_EDEVICE, "%s: %s", who, hipGetErrorString(err));
+        if (sdev != dev)
+            return fail(SP_EINVAL, "%s: the stream belongs to device %d, the current device is %d",
+                        who, (int)sdev, dev);
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (err != hipSuccess || !p)
+            return fail(SP_EDEVICE, "%s: no device address for the scratch array: %s", who,
+                        hipGetErrorString(err));
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return SP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -834,6 +876,23 @@ int sp_energy(const sp_grid *g, const sp_coeffs *c, double dt, double dx, const 
     if (reinterpret_cast<uintptr_t>(ws) & 7u) return fail(SP_EINVAL, "sp_energy: misaligned pointer");
     if ((int64_t)nblk * 8 > sp_energy_ws_bytes(g)) return fail(SP_ENOMEM, "sp_energy: workspace too small");
     return energy_launch("sp_energy", a, t, nblk, static_cast<double *>(ws), out, stream);
+}
+
+int64_t sp_energy_noalloc_max_partials(void) { return kScratchPartials; }
+
+int sp_energy_noalloc(const sp_grid *g, const sp_coeffs *c, double dt, double dx, const sp_grid *gv,
+                      const float *v, const void *u0, const void *u1, double *out, void *stream) {
+    sp::SweepArgs a;
+    sp::TileCfg t;
+    int nblk = 0;
+    const char *who = "sp_energy_noalloc";
+    if (int e = energy_prep(who, g, c, dt, dx, gv, v, u0, u1, out, &a, &t, &nblk)) return e;
+    if (nblk > kScratchPartials)
+        return fail(SP_ENOMEM, "%s: the sweep needs %d partial sums, the static scratch holds %d",
+                    who, nblk, kScratchPartials);
+    double *partial = nullptr;
+    if (int e = scratch_for_device(who, stream, &partial)) return e;
+    return energy_launch(who, a, t, nblk, partial, out, stream);
 }
 
 }  // extern "C"

@@ -26,7 +26,7 @@ ERROR_NAMES = {0: "SP_OK", 1: "SP_EINVAL", 2: "SP_EUNSUPPORTED", 3: "SP_EDEVICE"
 EXPORTS = [
     "sp_grid_init", "sp_grid_init_2d", "sp_stencil_apply", "sp_apply", "sp_wave_meta_bytes", "sp_wave_step",
     "sp_wave_step_fused", "sp_wave_run_states", "sp_wave_adjoint_step", "sp_grad_finish", "sp_decode", "sp_energy_ws_bytes",
-    "sp_energy", "sp_pml_profile", "sp_wave_step_pml", "sp_shot_bytes", "sp_queue_create", "sp_submit", "sp_poll", "sp_queue_drain",
+    "sp_energy", "sp_energy_noalloc_max_partials", "sp_energy_noalloc", "sp_pml_profile", "sp_wave_step_pml", "sp_shot_bytes", "sp_queue_create", "sp_submit", "sp_poll", "sp_queue_drain",
     "sp_queue_destroy", "sp_last_error", "sp_version",
 ]
 
@@ -136,6 +136,9 @@ def load():
     lib.sp_energy_ws_bytes.argtypes = [P(sp_grid)]
     lib.sp_energy_ws_bytes.restype = i64
     lib.sp_energy.argtypes = [P(sp_grid), P(sp_coeffs), d, d, P(sp_grid), vp, vp, vp, vp, vp, vp]
+    lib.sp_energy_noalloc_max_partials.argtypes = []
+    lib.sp_energy_noalloc_max_partials.restype = i64
+    lib.sp_energy_noalloc.argtypes = [P(sp_grid), P(sp_coeffs), d, d, P(sp_grid), vp, vp, vp, vp, vp]
     lib.sp_pml_profile.argtypes = [P(sp_grid), i, d, vp, vp]
     lib.sp_wave_step_pml.argtypes = [P(sp_grid), P(sp_coeffs), d, d, P(sp_grid), vp, P(sp_wave_state), i,
                                      P(sp_pml), P(sp_sources), P(sp_receivers), vp]
@@ -150,8 +153,8 @@ def load():
     lib.sp_version.restype = ctypes.c_char_p
     for name in EXPORTS:
         fn = getattr(lib, name)
-        if name not in ("sp_wave_meta_bytes", "sp_energy_ws_bytes", "sp_shot_bytes", "sp_last_error",
-                        "sp_version"):
+        if name not in ("sp_wave_meta_bytes", "sp_energy_ws_bytes", "sp_energy_noalloc_max_partials",
+                        "sp_shot_bytes", "sp_last_error", "sp_version"):
             fn.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -315,3 +318,9 @@ def sp_energy(g, c, dt, dx, gv, v_ptr, u0_ptr, u1_ptr, out_ptr, ws_ptr, stream=N
     check(load().sp_energy(ctypes.byref(g), ctypes.byref(c), float(dt), float(dx), ctypes.byref(gv),
                            ctypes.c_void_p(v_ptr), ctypes.c_void_p(u0_ptr), ctypes.c_void_p(u1_ptr),
                            ctypes.c_void_p(out_ptr), ctypes.c_void_p(ws_ptr), stream_ptr(stream)))
+
+
+def sp_energy_noalloc(g, c, dt, dx, gv, v_ptr, u0_ptr, u1_ptr, out_ptr, stream=None):
+    check(load().sp_energy_noalloc(ctypes.byref(g), ctypes.byref(c), float(dt), float(dx),
+                                   ctypes.byref(gv), ctypes.c_void_p(v_ptr), ctypes.c_void_p(u0_ptr),
+                                   ctypes.c_void_p(u1_ptr), ctypes.c_void_p(out_ptr), stream_ptr(stream)))
