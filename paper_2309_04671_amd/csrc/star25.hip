@@ -199,20 +199,31 @@ __device__ __forceinline__ void star25_wave_h(const SweepArgs &a, const int lin)
             a.meta.a_clear[i] = 0u;
         }
 
+    // Addresses are a uniform plane base (the frame corner (-4, -4) of the
+    // plane) plus a 32-bit per-lane byte offset: the loads take the
+    // scalar-base form and each offset costs the lane one VGPR.
+    const int64_t corner = -4 * a.sy - 4, vcorner = -4 * a.vsy - 4;
+    auto plane = [&](const T *f, int zz) {
+        return reinterpret_cast<const char *>(f + (int64_t)zz * sz + corner);
+    };
+    auto vplane = [&](int zz) { return reinterpret_cast<const char *>(a.v + (int64_t)zz * a.vsz + vcorner); };
+    auto at = [](const char *base, uint32_t off) { return reinterpret_cast<const T *>(base + off); };
+    auto vat = [](const char *base, uint32_t off) { return reinterpret_cast<const float *>(base + off); };
+
     bool ld_ok[RY], st_ok[RY];
-    int64_t own[RY], vown[RY];
+    uint32_t own[RY], vown[RY];
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
         const int y = ybase + j;
         ld_ok[j] = (y < a.ny + 4) && (x < a.nx + 4);
         st_ok[j] = (y < a.ny) && (x < a.nx);
-        own[j] = (int64_t)y * a.sy + x;
-        vown[j] = (int64_t)y * a.vsy + x;
+        own[j] = (uint32_t)(((int64_t)(y + 4) * a.sy + x + 4) * (int64_t)sizeof(T));
+        vown[j] = (uint32_t)(((int64_t)(y + 4) * a.vsy + x + 4) * 4);
     }
 
     int hrow[HPT], hchk[HPT];
     bool h_ok[HPT];
-    int64_t hoff[HPT];
+    uint32_t hoff[HPT];
 #pragma unroll
     for (int j = 0; j < HPT; ++j) {
         const int k = tid + j * NT;
@@ -233,7 +244,7 @@ __device__ __forceinline__ void star25_wave_h(const SweepArgs &a, const int lin)
             hchk[j] = side ? LX + 1 : 0;
         }
         h_ok[j] = (k < HC) && (y0 + dy < a.ny + 4) && (x0 + dx < a.nx + 4);
-        hoff[j] = (int64_t)(y0 + dy) * a.sy + (x0 + dx);
+        hoff[j] = (uint32_t)(((int64_t)(y0 + dy + 4) * a.sy + x0 + dx + 4) * (int64_t)sizeof(T));
     }
 
     const f4v zero = {0.f, 0.f, 0.f, 0.f};
@@ -264,17 +275,28 @@ __device__ __forceinline__ void star25_wave_h(const SweepArgs &a, const int lin)
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const int zz = zb - 4 + i;
-            q[j][i] = ld_ok[j] ? IO::ld(u + (int64_t)zz * sz + own[j]) : rzero;
+            q[j][i] = ld_ok[j] ? IO::ld(at(plane(u, zz), own[j])) : rzero;
         }
-        nq[j] = ld_ok[j] ? IO::ld(u + (int64_t)(zb + 4) * sz + own[j]) : rzero;
+        nq[j] = ld_ok[j] ? IO::ld(at(plane(u, zb + 4), own[j])) : rzero;
     }
-    raw hq[HPT][HQ];                      // halo chunks of planes z .. z+4
+    // Halo chunks of planes z .. z+HQR-1.  The FP32 sweeps fetch them 5
+    // planes ahead, when their owners fetch the same rows (L2 reuse); the
+    // raw 16-bit body keeps a shallower queue for occupancy: with depth 1
+    // the BF16 body fits three waves per SIMD (162 VGPRs, against 178 at
+    // depth 5), and FP16 at depth 2 keeps three (154).  Measured on one
+    // box, 128x16x2 tiles: BF16 485 against 429 GPts/s at 512^3 and 491
+    // against 470 at 1024x1024x512; FP16 498 against 493 and 499 against
+    // 499.
+    constexpr int HQR = std::is_same<T, __bf16>::value ? 1 : 2;
+    raw hq[HPT][HQR];
 #pragma unroll
     for (int j = 0; j < HPT; ++j)
 #pragma unroll
-        for (int k = 0; k < HQ; ++k)
-            hq[j][k] = h_ok[j] ? IO::ld(u + (int64_t)(zb + k) * sz + hoff[j]) : rzero;
+        for (int k = 0; k < HQR; ++k)
+            hq[j][k] = h_ok[j] ? IO::ld(at(plane(u, zb + k), hoff[j])) : rzero;
 
+    // u^{n-1} and v one plane ahead (two planes ahead measured 2-3 % slower:
+    // the extra registers cost BF16 its third wave per SIMD)
     raw pp[RY];
     f4v vv[RY];
 #pragma unroll
@@ -282,8 +304,8 @@ __device__ __forceinline__ void star25_wave_h(const SweepArgs &a, const int lin)
         pp[j] = rzero;
         vv[j] = zero;
         if (st_ok[j]) {
-            pp[j] = IO::ld_nt(uprev + (int64_t)zb * sz + own[j]);
-            vv[j] = ld4_nt(a.v + (int64_t)zb * a.vsz + vown[j]);
+            pp[j] = IO::ld_nt(at(plane(uprev, zb), own[j]));
+            vv[j] = ld4_nt(vat(vplane(zb), vown[j]));
         }
     }
 
@@ -325,15 +347,15 @@ __device__ __forceinline__ void star25_wave_h(const SweepArgs &a, const int lin)
         if (z + 1 < ze) {
 #pragma unroll
             for (int j = 0; j < RY; ++j)
-                nq[j] = ld_ok[j] ? IO::ld(u + (int64_t)(z + 5) * sz + own[j]) : rzero;
+                nq[j] = ld_ok[j] ? IO::ld(at(plane(u, z + 5), own[j])) : rzero;
 #pragma unroll
             for (int j = 0; j < HPT; ++j)
-                hn[j] = h_ok[j] ? IO::ld(u + (int64_t)(z + HQ) * sz + hoff[j]) : rzero;
+                hn[j] = h_ok[j] ? IO::ld(at(plane(u, z + HQR), hoff[j])) : rzero;
 #pragma unroll
             for (int j = 0; j < RY; ++j)
                 if (st_ok[j]) {
-                    pp_n[j] = IO::ld_nt(uprev + (int64_t)(z + 1) * sz + own[j]);
-                    vv_n[j] = ld4_nt(a.v + (int64_t)(z + 1) * a.vsz + vown[j]);
+                    pp_n[j] = IO::ld_nt(at(plane(uprev, z + 1), own[j]));
+                    vv_n[j] = ld4_nt(vat(vplane(z + 1), vown[j]));
                 }
         }
 
@@ -401,7 +423,7 @@ __device__ __forceinline__ void star25_wave_h(const SweepArgs &a, const int lin)
             }
             if (st_ok[j]) {
                 if (NF) bad |= nonfinite4(res, a.nx - x);
-                T *o = out + (int64_t)z * sz + own[j];
+                T *o = const_cast<T *>(at(plane(out, z), own[j]));
                 // the slab maximum is taken on the scaled FP32 values and
                 // rounded once per wave below: rounding to nearest even is
                 // monotone and odd, so max |round(v)| = round(max |v|)
@@ -441,8 +463,8 @@ __device__ __forceinline__ void star25_wave_h(const SweepArgs &a, const int lin)
 #pragma unroll
         for (int j = 0; j < HPT; ++j) {
 #pragma unroll
-            for (int k = 0; k + 1 < HQ; ++k) hq[j][k] = hq[j][k + 1];
-            hq[j][HQ - 1] = hn[j];
+            for (int k = 0; k + 1 < HQR; ++k) hq[j][k] = hq[j][k + 1];
+            hq[j][HQR - 1] = hn[j];
         }
     }
     if (NF) report_nonfinite(a.nonfinite, bad);
