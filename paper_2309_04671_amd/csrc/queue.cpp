@@ -29,13 +29,13 @@ double now_s() {
 int64_t align256(int64_t b) { return (b + 255) / 256 * 256; }
 
 // Planes per block of a shot that shares its launch with other shots.  A
-// lone grid is split along z only as far as it needs to fill the GPU; in a
-// batch the other shots supply that parallelism, and short, equal chunks
-// keep the launch's tail short.  Measured on a saturating batch of the four
-// served shapes: 16 beats the lone-grid split by 1.8 % in capacity, 8 and 12
-// lose to the re-read start-up planes, 24 and longer to the tail.  A shot
-// alone in its launch keeps its own split.  The z-split never changes a
-// point's arithmetic.
+// lone grid is split along z as far as it needs to fill the GPU (a small
+// grid into chunks shorter than this); in a batch the other shots supply
+// that parallelism, and short, equal chunks keep the launch's tail short.
+// Measured on a saturating batch of the four served shapes: 16 beats the
+// lone-grid split by 1.8 % in capacity, 8 and 12 lose to the re-read
+// start-up planes, 24 and longer to the tail.  A shot alone in its launch
+// keeps its own split.  The z-split never changes a point's arithmetic.
 constexpr int QUEUE_ZCHUNK = 16;
 
 // Same block -> tile map as the single-grid kernels (contiguous per XCD).
@@ -209,7 +209,7 @@ int rebuild(sp_queue *q, const std::vector<Shot *> &act, int k) {
     }
     for (auto &g : q->groups) {
         for (Shot *m : g.members) {
-            const int zc = g.members.size() > 1 ? std::min(m->base.zchunk, QUEUE_ZCHUNK) : m->base.zchunk;
+            const int zc = g.members.size() > 1 ? std::min(QUEUE_ZCHUNK, m->g.nz) : m->base.zchunk;
             m->run = m->base;
             m->run.zchunk = zc;
             m->run.nzc = (m->g.nz + zc - 1) / zc;
@@ -569,8 +569,12 @@ int sp_submit(sp_queue *q, const sp_shot_desc *d, uint64_t *ticket) {
                               reinterpret_cast<const float *>(q->cfg.arena), d->nsrc ? &src : nullptr,
                               d->nrec ? &rec : nullptr, &s.base, &s.tile))
         return e;
-    s.nblk = s.base.tiles_x * s.base.tiles_y * ((s.g.nz + std::min(s.base.zchunk, QUEUE_ZCHUNK) - 1) /
-                                                std::min(s.base.zchunk, QUEUE_ZCHUNK));
+    {
+        // blocks at the larger of the two z-splits (alone: its own; batched: QUEUE_ZCHUNK)
+        const int zb = std::min(QUEUE_ZCHUNK, s.g.nz), zs = s.base.zchunk;
+        s.nblk = s.base.tiles_x * s.base.tiles_y *
+                 std::max((s.g.nz + zb - 1) / zb, (s.g.nz + zs - 1) / zs);
+    }
     if (!sp::batch_supported(s.tile))
         return fail(SP_EUNSUPPORTED, "sp_submit: tile configuration %dx%dx%d is not batched",
                     s.tile.tx, s.tile.ty, s.tile.ry);
