@@ -98,7 +98,7 @@ bool tiles_for(const sp_grid *g, sp::TileCfg *out, const char *who, int mode = s
         if (n == 4 && zc > 0) t.zchunk = std::min(zc, g->nz);
     }
     if (g->dtype != SP_F32 && t.zchunk > sp::MAX_ZCHUNK_SCALED) t.zchunk = sp::MAX_ZCHUNK_SCALED;
-    if (!sp::tile_supported(t)) {
+    if (!sp::tile_supported(t, mode)) {
         fail(SP_EINVAL, "%s: tile configuration %dx%dx%d is not compiled in", who, t.tx, t.ty, t.ry);
         return false;
     }

@@ -103,7 +103,7 @@ struct BoxSet {
 hipError_t launch_sweep_boxes(int mode, const BoxSet &bs, hipStream_t s);
 // Configurations the batched (multi-grid) sweep is compiled for.
 bool batch_supported(const TileCfg &t);
-bool tile_supported(const TileCfg &t);
+bool tile_supported(const TileCfg &t, int mode);
 hipError_t launch_sweep(int mode, int dtype, const TileCfg &t, const SweepArgs &a, hipStream_t s);
 // Record u at receiver points (decoding with per-slab scales if `scale`).
 hipError_t launch_record(int dtype, const void *u, const float *scale, int64_t sy, int64_t sz,

@@ -273,6 +273,29 @@ def test_c3_gradient_vs_checkpointed_oracle(gpu_lib, c3, capsys):
     assert e_own["rel_l2"] <= 10 * e_res + 1e-4
 
 
+def test_fused_adjoint_on_its_wide_tiles_matches_oracle(gpu_lib):
+    # A ragged grid on which the fused adjoint sweep takes its 128x16x1
+    # tiles (two tiles across x, the second mostly past the edge; several
+    # z-chunks): the misfit gradient against the oracle's adjoint.
+    from paper_2309_04671_amd.adjoint import misfit_gradient
+    nx, ny, nz, steps = 250, 37, 44, 40
+    v = synth.gaussian_bump(synth.layered_velocity(nx, ny, nz, 5), (120, 18, 20), 5.0, 0.1)
+    dx = 10.0
+    dt = synth.cfl_dt(v, dx)
+    co = synth.star25_coeffs()
+    src = np.array([[120, 18, 8]], np.int32)
+    rec = synth.receiver_plane(nx, ny, 14, 3)
+    amp = (synth.ricker(steps, dt, 40.0)[:, None] * 1e4).astype(np.float32).astype(np.float64)
+    obs = np.zeros((steps, len(rec)))
+    J_ref, g_ref = oracle.adjoint_grad(co, v, dt, dx, steps, src, amp, rec, obs)
+    prob = _problem(co, v, dt, dx, steps, src, amp, rec, ckpt=7)
+    J, g = misfit_gradient(torch.tensor(v, device="cuda"), prob, torch.zeros((steps, len(rec)), device="cuda"))
+    e = errors(g.cpu().numpy(), g_ref)
+    print("fused adjoint, 128x16x1 tiles, %dx%dx%d: J %.6e vs %.6e, gradient %s" % (nx, ny, nz, J, J_ref, e))
+    assert abs(J - J_ref) <= 1e-5 * J_ref
+    assert e["rel_l2"] <= 1e-4
+
+
 TILE_CONFIGS = ["64x16x1", "128x16x2", "128x32x2", "256x16x2", "256x8x2", "256x16x1", "256x8x1",
                 "64x16x1x7", "128x16x2x33", "256x16x2x40", "256x8x1x9"]
 
