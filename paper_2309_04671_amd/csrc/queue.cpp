@@ -124,6 +124,7 @@ struct sp_queue {
     bool fake = false, eager = false;
     int device = 0;
     hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;    // graph capture only (never executes work)
     hipEvent_t chunk_done = nullptr;
     char *ctrl_dev = nullptr;            // control part of the arena (tables, per-step args)
     int64_t ctrl_bytes = 0, budget = 0, resident = 0;
@@ -186,8 +187,8 @@ void destroy_graph(sp_queue *q) {
     q->graph = nullptr;
 }
 
-// Lay out the control part for the active set and k steps per chunk, upload
-// the static tables, and capture the chunk graph.
+// Lay out the control part for the active set and k steps per chunk and
+// upload the static tables (the chunk graph is captured by the first chunk).
 int rebuild(sp_queue *q, const std::vector<Shot *> &act, int k) {
     destroy_graph(q);
     q->groups.clear();
@@ -258,29 +259,46 @@ int rebuild(sp_queue *q, const std::vector<Shot *> &act, int k) {
         hipError_t e = hipMemcpyAsync(q->ctrl_dev, q->pinned, static_end, hipMemcpyHostToDevice, q->stream);
         if (e != hipSuccess) return fail(SP_EDEVICE, "queue: table upload: %s", hipGetErrorString(e));
     }
-    if (q->eager) return SP_OK;
-    hipError_t e = hipStreamBeginCapture(q->stream, hipStreamCaptureModeThreadLocal);
+    return SP_OK;
+}
+
+// The k steps of the current composition: per step and group one batched
+// sweep and one batched receiver launch, reading their arguments from the
+// control part.
+hipError_t launch_steps(sp_queue *q, int k, hipStream_t st) {
+    hipError_t e = hipSuccess;
     for (int i = 0; i < k && e == hipSuccess; ++i) {
         for (auto &g : q->groups) {
             const int nm = (int)g.members.size();
             auto *args = reinterpret_cast<const sp::SweepArgs *>(q->ctrl_dev + g.off_args) + (int64_t)i * nm;
             auto *table = reinterpret_cast<const int2 *>(q->ctrl_dev + g.off_table);
-            e = sp::launch_sweep_batch(sp::MODE_WAVE, g.dtype, g.tile, args, table, g.nblk, q->stream);
+            e = sp::launch_sweep_batch(sp::MODE_WAVE, g.dtype, g.tile, args, table, g.nblk, st);
             if (e == hipSuccess && g.nrec > 0) {
                 auto *recs = reinterpret_cast<const sp::RecArgs *>(q->ctrl_dev + g.off_recs) + (int64_t)i * nm;
                 auto *rmap = reinterpret_cast<const int2 *>(q->ctrl_dev + g.off_rmap);
-                e = sp::launch_record_batch(g.dtype, recs, rmap, g.nrec, q->stream);
+                e = sp::launch_record_batch(g.dtype, recs, rmap, g.nrec, st);
             }
             if (e != hipSuccess) break;
         }
     }
+    return e;
+}
+
+// Capture the current composition's chunk into a graph on the capture-only
+// stream (nothing executes there).  Called right after the composition's
+// first chunk was launched directly, so the capture and instantiation run
+// on the host while the GPU works, off the chunks' critical path.  On
+// failure the composition keeps launching directly.
+void capture_chunk(sp_queue *q, int k) {
+    hipError_t e = hipStreamBeginCapture(q->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return;
+    e = launch_steps(q, k, q->cap_stream);
     hipGraph_t graph = nullptr;
-    hipError_t e2 = hipStreamEndCapture(q->stream, &graph);
+    const hipError_t e2 = hipStreamEndCapture(q->cap_stream, &graph);
     if (e == hipSuccess) e = e2;
     if (e == hipSuccess) e = hipGraphInstantiate(&q->exec, graph, nullptr, nullptr, 0);
     q->graph = graph;
-    if (e != hipSuccess) return fail(SP_EDEVICE, "queue: graph capture: %s", hipGetErrorString(e));
-    return SP_OK;
+    if (e != hipSuccess) destroy_graph(q);
 }
 
 // Fill the per-step arguments of the next k steps and run them.
@@ -323,25 +341,20 @@ int run_chunk(sp_queue *q, int k) {
     if (q->dyn_bytes > 0)
         e = hipMemcpyAsync(q->ctrl_dev + q->dyn_off, q->pinned + q->dyn_off, q->dyn_bytes,
                            hipMemcpyHostToDevice, q->stream);
+    // A composition's first chunk is launched directly and its graph
+    // captured while that chunk runs; later chunks of the same composition
+    // replay the graph.  Short-lived compositions never pay for a capture
+    // on the critical path.
+    bool capture = false;
     if (e == hipSuccess) {
-        if (q->eager) {
-            for (int i = 0; i < k && e == hipSuccess; ++i)
-                for (auto &g : q->groups) {
-                    const int nm = (int)g.members.size();
-                    auto *args = reinterpret_cast<const sp::SweepArgs *>(q->ctrl_dev + g.off_args) + (int64_t)i * nm;
-                    e = sp::launch_sweep_batch(sp::MODE_WAVE, g.dtype, g.tile, args,
-                                               reinterpret_cast<const int2 *>(q->ctrl_dev + g.off_table),
-                                               g.nblk, q->stream);
-                    if (e == hipSuccess && g.nrec > 0)
-                        e = sp::launch_record_batch(
-                            g.dtype, reinterpret_cast<const sp::RecArgs *>(q->ctrl_dev + g.off_recs) + (int64_t)i * nm,
-                            reinterpret_cast<const int2 *>(q->ctrl_dev + g.off_rmap), g.nrec, q->stream);
-                    if (e != hipSuccess) break;
-                }
-        } else {
+        if (q->exec) {
             e = hipGraphLaunch(q->exec, q->stream);
+        } else {
+            e = launch_steps(q, k, q->stream);
+            capture = !q->eager;
         }
     }
+    if (e == hipSuccess && capture) capture_chunk(q, k);
     // the resident shots' non-finite flags, read back with the chunk
     int nflag = 0;
     for (auto &g : q->groups)
@@ -529,6 +542,7 @@ int sp_queue_create(const sp_queue_cfg *cfg, sp_queue **out) {
     if (!q->fake) {
         hipError_t e = hipGetDevice(&q->device);
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&q->stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&q->cap_stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&q->chunk_done, hipEventDisableTiming);
         if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&q->pinned), q->ctrl_bytes, hipHostMallocDefault);
         if (e == hipSuccess)
@@ -536,6 +550,7 @@ int sp_queue_create(const sp_queue_cfg *cfg, sp_queue **out) {
                               sizeof(uint32_t) * (size_t)cfg->max_slots, hipHostMallocDefault);
         if (e != hipSuccess) {
             if (q->pinned) (void)hipHostFree(q->pinned);
+            if (q->cap_stream) (void)hipStreamDestroy(q->cap_stream);
             if (q->stream) (void)hipStreamDestroy(q->stream);
             if (q->chunk_done) (void)hipEventDestroy(q->chunk_done);
             delete q;
@@ -651,6 +666,7 @@ int sp_queue_destroy(sp_queue *q) {
             if (kv.second.ready) (void)hipEventDestroy(kv.second.ready);
         (void)hipStreamSynchronize(q->stream);
         (void)hipEventDestroy(q->chunk_done);
+        (void)hipStreamDestroy(q->cap_stream);
         (void)hipStreamDestroy(q->stream);
         (void)hipHostFree(q->pinned);
         (void)hipHostFree(q->flags_host);
