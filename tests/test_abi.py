@@ -228,3 +228,54 @@ def test_suite_apply_validates_before_launch():
     assert call(forged, box) == lib.SP_EINVAL
     # sweeps = 0 is a no-op that launches nothing
     assert call(g3, box, sweeps=0) == lib.SP_OK and out.value == 0
+
+
+def test_decode_validates_before_launch():
+    L = lib.load()
+    g = lib.grid_init(32, 32, 32)
+    g16 = lib.grid_init(32, 32, 32, dtype=lib.SP_F16)
+    f, out = ctypes.c_void_p(1 << 30), ctypes.c_void_p(1 << 36)
+    assert L.sp_decode(None, f, None, 0, out, None) == lib.SP_EINVAL
+    assert L.sp_decode(ctypes.byref(g), None, None, 0, out, None) == lib.SP_EINVAL
+    assert L.sp_decode(ctypes.byref(g), f, None, 0, None, None) == lib.SP_EINVAL
+    # FP16/BF16 fields need their slab records
+    assert L.sp_decode(ctypes.byref(g16), f, None, 0, out, None) == lib.SP_EINVAL
+    assert "slab records" in lib.last_error()
+    # out may not overlap the field
+    assert L.sp_decode(ctypes.byref(g), f, None, 0, ctypes.c_void_p((1 << 30) + 4096), None) == lib.SP_EINVAL
+    assert "overlaps" in lib.last_error()
+    bad = lib.grid_init(32, 32, 32)
+    bad.pitch_x += 1
+    assert L.sp_decode(ctypes.byref(bad), f, None, 0, out, None) == lib.SP_EINVAL
+
+
+def test_energy_noalloc_validates_before_launch():
+    L = lib.load()
+    assert L.sp_energy_noalloc_max_partials() == 1 << 16
+    g = lib.grid_init(32, 32, 32)
+    c = lib.coeffs({"center": -1, "ax": [0] * 4, "ay": [0] * 4, "az": [0] * 4})
+    v, u0, u1 = ctypes.c_void_p(1 << 40), ctypes.c_void_p(1 << 30), ctypes.c_void_p(1 << 36)
+    out = ctypes.c_void_p(1 << 38)
+
+    def call(**kw):
+        a = dict(g=g, dt=1e-3, u0=u0, u1=u1, out=out)
+        a.update(kw)
+        return L.sp_energy_noalloc(ctypes.byref(a["g"]), ctypes.byref(c), a["dt"], 10.0, ctypes.byref(g),
+                                   v, a["u0"], a["u1"], a["out"], None)
+
+    assert call(dt=0.0) == lib.SP_EINVAL
+    assert call(u0=None) == lib.SP_EINVAL
+    assert call(out=ctypes.c_void_p((1 << 38) + 4)) == lib.SP_EINVAL and "misaligned" in lib.last_error()
+    assert call(g=lib.grid_init(32, 32, 32, dtype=lib.SP_F16)) in (lib.SP_EINVAL, lib.SP_EUNSUPPORTED)
+
+
+def test_adjoint_only_tile_is_rejected_for_other_sweeps(monkeypatch):
+    # 128x16x1 is compiled for the fused adjoint sweep only
+    monkeypatch.setenv("SP_TILE", "128x16x1")
+    L = lib.load()
+    g = lib.grid_init(16, 16, 16)
+    c = lib.coeffs({"center": -1, "ax": [0] * 4, "ay": [0] * 4, "az": [0] * 4})
+    out = ctypes.c_int()
+    rc = L.sp_stencil_apply(ctypes.byref(g), ctypes.byref(c), 1, ctypes.c_void_p(1 << 30),
+                            ctypes.c_void_p(1 << 40), ctypes.byref(out), None)
+    assert rc == lib.SP_EINVAL and "not compiled" in lib.last_error()
