@@ -12,6 +12,7 @@
 #include <mutex>
 
 #include "internal.h"
+#include "log.h"
 
 namespace {
 thread_local char g_err[512] = "";
@@ -30,6 +31,24 @@ int fail(int code, const char *fmt, ...) {
 int ok() {
     g_err[0] = '\0';
     return SP_OK;
+}
+
+bool log_on() {
+    static const bool on = [] {
+        const char *e = std::getenv("SP_LOG");
+        return e && e[0] && std::strcmp(e, "0") != 0;
+    }();
+    return on;
+}
+
+void log_line(const char *fmt, ...) {
+    if (!log_on()) return;
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    std::fprintf(stderr, "[libstencil] %s\n", buf);
 }
 
 }  // namespace sp
@@ -101,6 +120,12 @@ bool tiles_for(const sp_grid *g, sp::TileCfg *out, const char *who, int mode = s
     if (!sp::tile_supported(t, mode)) {
         fail(SP_EINVAL, "%s: tile configuration %dx%dx%d is not compiled in", who, t.tx, t.ty, t.ry);
         return false;
+    }
+    if (sp::log_on()) {
+        const int64_t blocks = (int64_t)((g->nx + t.tx - 1) / t.tx) * ((g->ny + t.ty - 1) / t.ty) *
+                               ((g->nz + t.zchunk - 1) / t.zchunk);
+        sp::log_line("%s: %dx%dx%d dtype %d mode %d -> tile %dx%dx%d, z-chunk %d, %lld blocks", who,
+                     g->nx, g->ny, g->nz, g->dtype, mode, t.tx, t.ty, t.ry, t.zchunk, (long long)blocks);
     }
     *out = t;
     return true;

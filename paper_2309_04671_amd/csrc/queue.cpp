@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "log.h"
 
 namespace {
 
@@ -236,6 +237,12 @@ int rebuild(sp_queue *q, const std::vector<Shot *> &act, int k) {
     }
     q->dyn_bytes = off - q->dyn_off;
     if (off > q->ctrl_bytes) return fail(SP_ENOMEM, "queue: control data exceeds its arena part");
+    if (sp::log_on()) {
+        int blocks = 0;
+        for (auto &g : q->groups) blocks += g.nblk;
+        sp::log_line("queue: composition of %zu shots in %zu groups, %d blocks per step, %d steps per chunk",
+                     act.size(), q->groups.size(), blocks, k);
+    }
     q->comp_ids.clear();
     for (Shot *a : act) q->comp_ids.push_back(a->id);
     q->comp_k = k;
@@ -444,6 +451,11 @@ void worker_main(sp_queue *q) {
                 s.cur = s.f1;
                 s.prev = s.f0;
                 s.state = SP_SHOT_RUNNING;
+                sp::log_line("queue: admit ticket %llu, %dx%dx%d dtype %d, %d steps, %lld bytes "
+                             "(resident %lld of %lld), waited %.4f s",
+                             (unsigned long long)s.id, s.g.nx, s.g.ny, s.g.nz, s.g.dtype, s.d.nsteps,
+                             (long long)s.bytes, (long long)q->resident, (long long)q->budget,
+                             s.t_admit - s.t_submit);
                 q->active.push_back(s.id);
                 fresh.push_back(&s);
             }
@@ -495,6 +507,9 @@ void worker_main(sp_queue *q) {
                 } else {
                     s.t_done = now_s();
                     release_shot(q, s);
+                    sp::log_line("queue: ticket %llu %s (error %d) after %lld steps, latency %.4f s",
+                                 (unsigned long long)s.id, s.state == SP_SHOT_DONE ? "done" : "failed",
+                                 s.error, (long long)s.step, s.t_done - s.t_submit);
                 }
             }
             q->active.swap(still);

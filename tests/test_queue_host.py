@@ -189,3 +189,42 @@ def test_mixed_shapes_and_types(dtype):
         rc, st = status(q, t)
         assert rc == lib.SP_OK and st.state == lib.SP_SHOT_DONE and st.steps_done == 17 + k
     lib.check(L.sp_queue_destroy(q))
+
+
+def test_library_log_reports_launch_choices_and_queue_events():
+    # SP_LOG=1 (read once per process, hence a child process): the tile
+    # choice of a launch and the queue's admissions, compositions and
+    # retirements go to stderr
+    import subprocess
+    import sys
+    import textwrap
+    root = __import__("os").path.dirname(__import__("os").path.dirname(__import__("os").path.abspath(__file__)))
+    code = textwrap.dedent('''
+        import ctypes, sys
+        sys.path.insert(0, %r)
+        from tests.test_queue_host import desc, make_queue, submit
+        from paper_2309_04671_amd import lib
+        L = lib.load()
+        q = make_queue(1 << 30, slots=2, chunk=5)
+        for k in range(3):
+            submit(q, desc(48, 12))
+        lib.check(L.sp_queue_drain(q))
+        lib.check(L.sp_queue_destroy(q))
+        g = lib.grid_init(64, 64, 64)
+        c = lib.coeffs({"center": -1, "ax": [0.1] * 4, "ay": [0.1] * 4, "az": [0.1] * 4})
+        out = ctypes.c_int()
+        L.sp_stencil_apply(ctypes.byref(g), ctypes.byref(c), 0, ctypes.c_void_p(1 << 30),
+                           ctypes.c_void_p(1 << 40), ctypes.byref(out), None)
+    ''' % root)
+    env = dict(__import__("os").environ, SP_LOG="1")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    lines = [l for l in r.stderr.splitlines() if l.startswith("[libstencil]")]
+    assert sum("queue: admit ticket" in l for l in lines) == 3
+    assert sum("queue: ticket" in l and " done " in l for l in lines) == 3
+    assert any("queue: composition of " in l and "blocks per step" in l for l in lines)
+    assert any("sp_stencil_apply: 64x64x64" in l and "z-chunk 1" in l for l in lines)
+    # without SP_LOG nothing is printed
+    env.pop("SP_LOG")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0 and "[libstencil]" not in r.stderr
