@@ -153,6 +153,8 @@ int sp_apply(const sp_grid *g, const sp_stencil *s, int sweeps, void *u, void *v
  * u^j uses slot j mod 4 (u^{-1}: slot 3).  Slot layout, nslab = ceil(nz/16):
  *     float    scale[nslab];   s_k
  *     uint32_t amax[nslab];    IEEE bits of max |q| * s_k over slab k
+ * FP16/BF16 storage needs planes of fewer than 2^30 elements (pitch_x x
+ * pitch_y of the FP32 v grid; SP_EUNSUPPORTED otherwise).
  * Zero-fill the block before the first step from zero fields; to start from
  * non-zero fields, fill slots 0 (u^0) and 3 (u^{-1}) consistently.  Step n
  * chooses s_k of u^{n+1} before computing it:

@@ -288,6 +288,10 @@ int prep_wave(const char *who, const sp_grid *g, const sp_coeffs *c, double dt, 
     if (!c || !v) return fail(SP_EINVAL, "%s: NULL argument", who);
     if (!(dt > 0) || !(dx > 0)) return fail(SP_EINVAL, "%s: dt and dx must be > 0", who);
     if (!aligned16(v)) return fail(SP_EINVAL, "%s: pointers must be 16-byte aligned", who);
+    // the 16-bit leapfrog addresses a plane with 32-bit byte offsets (its
+    // FP32 v plane included)
+    if (g->dtype != SP_F32 && gv->pitch_x * gv->pitch_y >= ((int64_t)1 << 30))
+        return fail(SP_EUNSUPPORTED, "%s: FP16/BF16 storage needs planes of fewer than 2^30 elements", who);
     int nsrc = 0;
     if (src) {
         if (src->n < 0 || src->n > SP_MAX_SOURCES)

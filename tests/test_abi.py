@@ -279,3 +279,17 @@ def test_adjoint_only_tile_is_rejected_for_other_sweeps(monkeypatch):
     rc = L.sp_stencil_apply(ctypes.byref(g), ctypes.byref(c), 1, ctypes.c_void_p(1 << 30),
                             ctypes.c_void_p(1 << 40), ctypes.byref(out), None)
     assert rc == lib.SP_EINVAL and "not compiled" in lib.last_error()
+
+
+def test_huge_planes_with_16bit_storage_are_refused():
+    # 32768 x 32768 planes (2^30 elements with the frame) are beyond the
+    # 32-bit plane offsets of the 16-bit leapfrog: refused before launch
+    L = lib.load()
+    g = lib.grid_init(32768, 32768, 1, dtype=lib.SP_F16)
+    gv = lib.grid_init(32768, 32768, 1)
+    c = lib.coeffs({"center": -1, "ax": [0] * 4, "ay": [0] * 4, "az": [0] * 4})
+    st = lib.sp_wave_state(1 << 40, 1 << 44, 1 << 46, 0)
+    rc = L.sp_wave_step(ctypes.byref(g), ctypes.byref(c), 1e-3, 10.0, ctypes.byref(gv), ctypes.c_void_p(1 << 42),
+                        ctypes.byref(st), 1, None, None, None)
+    assert rc == lib.SP_EUNSUPPORTED and "2^30" in lib.last_error()
+    assert st.step == 0
