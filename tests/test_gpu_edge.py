@@ -70,3 +70,51 @@ def test_zero_steps(gpu_lib, entry):
     assert _same(before, *everything)
     assert (ws.st.cur, ws.st.prev, list(ws.spare)) == ptrs
     assert ws.st.step == 2
+
+
+@pytest.mark.timeout(600)
+def test_leapfrog_beyond_2_32_elements_sampled(gpu_lib):
+    # The largest size class: a 2048 x 2048 x 1040 FP32 grid has more than
+    # 2^32 elements per field (17.9 GB each), so element offsets of its last
+    # planes need 64 bits.  One leapfrog step from a random state (inputs
+    # built on the device from a seeded generator), checked against the
+    # oracle at sampled points, many of them in the planes beyond 2^32.
+    from paper_2309_04671_amd import fields, lib
+    import oracle
+    nx, ny, nz = 2048, 2048, 1040
+    g = lib.grid_init(nx, ny, nz)
+    assert g.elems > 2 ** 32
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(11)
+    V, P, C = fields.Field(g), fields.Field(g), fields.Field(g)
+    speeds = np.random.default_rng(0).uniform(1500.0, 4500.0, 8)
+    for k in range(8):                           # 8 horizontal layers of 130 planes
+        V.interior()[k * 130:(k + 1) * 130].fill_(float(speeds[k]))
+    for F in (P, C):
+        for z0 in range(0, nz, 65):              # in slabs: uniform_ on a strided view
+            F.interior()[z0:z0 + 65].uniform_(-1.0, 1.0, generator=gen)
+    dx = 10.0
+    dt = 0.4 * dx / float(speeds.max())
+    co = synth.star25_coeffs()
+    st = lib.sp_wave_state(C.ptr, P.ptr, None, 0)
+    Pp = P.padded()
+    rng = np.random.default_rng(3)
+    pts = [(int(rng.integers(0, nx)), int(rng.integers(0, ny)), int(rng.integers(0, nz))) for _ in range(120)]
+    pts += [(int(rng.integers(0, nx)), int(rng.integers(0, ny)), int(rng.integers(1001, nz))) for _ in range(120)]
+    pts += [(x, y, z) for x in (0, nx - 1) for y in (0, ny - 1) for z in (0, nz - 1)]
+    # the neighbourhoods of u^{n-1} and u^n before the step (u^{n+1} overwrites u^{n-1})
+    before = [(Pp[z:z + 9, y:y + 9, x:x + 9].double().cpu().numpy(),
+               C.padded()[z:z + 9, y:y + 9, x:x + 9].double().cpu().numpy()) for (x, y, z) in pts]
+    lib.sp_wave_step(g, lib.coeffs(co), dt, dx, g, V.ptr, st, 1)
+    torch.cuda.synchronize()
+    out = (P if st.cur == P.ptr else C).padded()
+    got = np.array([float(out[z + 4, y + 4, x + 4]) for (x, y, z) in pts])
+    vi = V.interior()
+    ref = np.empty(len(pts))
+    for k, ((x, y, z), (pv, cu)) in enumerate(zip(pts, before)):
+        r = oracle.wave_run(co, np.array([[[float(vi[z, y, x])]]]), dt, dx, 1, prev=pv, cur=cu)
+        ref[k] = r["cur"][4, 4, 4]
+    e = np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 1.0))
+    print("2048x2048x1040 (%d elements per field), %d sampled points: max relative error %.2e"
+          % (g.elems, len(pts), e))
+    assert e <= 1e-5
