@@ -200,8 +200,8 @@ def leg_suite(torch, lib, fields, synth, sweeps=10, apply_only=False):
     c8 = synth.star25_coeffs()
     norm = abs(c8["center"]) + 2 * sum(abs(x) for k in ("ax", "ay", "az") for x in c8[k])
     co = lib.coeffs({"center": c8["center"] / norm, **{k: [x / norm for x in c8[k]] for k in ("ax", "ay", "az")}})
-    # C0: one 64^3 sweep is launch-latency bound (1.5 MB fits in L2); time
-    # per sweep over 1000 back-to-back sweeps
+    # one 64^3 sweep is latency-bound (1.5 MB fits in L2); time per sweep
+    # over 1000 back-to-back sweeps
     g = lib.grid_init(64, 64, 64)
     a, b = fields.Field(g), fields.Field(g)
     a.set_interior(torch.rand((64, 64, 64), generator=torch.Generator().manual_seed(0)))
@@ -212,7 +212,7 @@ def leg_suite(torch, lib, fields, synth, sweeps=10, apply_only=False):
     e1.record(stream)
     torch.cuda.synchronize()
     out["apply25_64^3_latency"] = {"us_per_sweep": round(e0.elapsed_time(e1), 2),
-                                   "note": "1000 back-to-back sweeps, launch-latency bound"}
+                                   "note": "1000 back-to-back sweeps, latency-bound (1-plane z-chunks)"}
     for n3 in ((512, 512, 512), (1024, 1024, 512)):
         g = lib.grid_init(*n3)
         ms, ok = timed(g, lambda g, a, b, k: lib.sp_stencil_apply(g, co, k, a.ptr, b.ptr, stream=stream))
@@ -350,9 +350,9 @@ def leg_storage_vs_oracle(torch, lib, fields, synth, n=128, nt=1000):
     return out
 
 
-def oracle_c0_and_adjoint(synth):
+def oracle_small_and_adjoint(synth):
     """The oracle beside the small forms, timed on the host cores: one
-    25-point sweep at 64^3 (C0), the misfit gradient at 48^3 x 200 steps
+    25-point sweep at 64^3, the misfit gradient at 48^3 x 200 steps
     (the gradient check's size), and bounded samples of the full-size ones:
     the checkpointed gradient at 256^3 over 24 steps (the adjoint workload's
     grid) and 10 leapfrog steps at 512^3 (the storage forms' grid)."""
@@ -862,7 +862,7 @@ def main():
         log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline()
         if forms:
-            c0, adj, adj256, st512 = oracle_c0_and_adjoint(synth)
+            c0, adj, adj256, st512 = oracle_small_and_adjoint(synth)
             if "suite" in forms or "apply" in forms:
                 forms["suite" if "suite" in forms else "apply"]["apply25_64^3_latency"]["oracle"] = c0
             if "adjoint_256" in forms:

@@ -51,7 +51,7 @@ def test_c0_single_sweep_parity(gpu_lib):
     got = v.get_interior()
     ref = oracle.laplacian(oracle.padded(u), co)
     e = errors(got, ref)
-    print("C0 64^3 sweep vs FP64 oracle:", e)
+    print("64^3 sweep vs FP64 oracle:", e)
     assert e["rel_l2"] <= TOL_SWEEP
 
 
