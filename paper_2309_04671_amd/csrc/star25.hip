@@ -283,10 +283,10 @@ __device__ __forceinline__ void star25_wave_h(const SweepArgs &a, const int lin)
     // planes ahead, when their owners fetch the same rows (L2 reuse); the
     // raw 16-bit body keeps a shallower queue for occupancy: with depth 1
     // the BF16 body fits three waves per SIMD (162 VGPRs, against 178 at
-    // depth 5), and FP16 at depth 2 keeps three (154).  Measured on one
-    // box, 128x16x2 tiles: BF16 485 against 429 GPts/s at 512^3 and 491
-    // against 470 at 1024x1024x512; FP16 498 against 493 and 499 against
-    // 499.
+    // depth 5), and FP16 at depth 2 keeps three (154).  Measured side by
+    // side on MI355X, 128x16x2 tiles: BF16 485 against 429 GPts/s at 512^3
+    // and 491 against 470 at 1024x1024x512; FP16 498 against 493 and 499
+    // against 499.
     constexpr int HQR = std::is_same<T, __bf16>::value ? 1 : 2;
     raw hq[HPT][HQR];
 #pragma unroll
