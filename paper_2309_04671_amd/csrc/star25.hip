@@ -162,7 +162,7 @@ __device__ float slab_scale(const SweepArgs &a, int k) {
 // records and rounding as the generic body; about half the queue and LDS
 // footprint.
 template <int TX, int TY, int RY, typename T, bool NF>
-__device__ __forceinline__ void star25_wave_h(const SweepArgs &a, const int lin) {
+__device__ __forceinline__ void star25_wave_raw16(const SweepArgs &a, const int lin) {
     typedef Io<T> IO;
     typedef typename IO::raw raw;
     constexpr int LX = TX / 4;
@@ -478,7 +478,7 @@ __device__ __forceinline__ void star25_wave_h(const SweepArgs &a, const int lin)
 template <int TX, int TY, int RY, int MODE, typename T, bool NF = false>
 __device__ __forceinline__ void star25_body(const SweepArgs &a, const int lin) {
     if constexpr (MODE == MODE_WAVE && Io<T>::scaled) {
-        star25_wave_h<TX, TY, RY, T, NF>(a, lin);
+        star25_wave_raw16<TX, TY, RY, T, NF>(a, lin);
         return;
     }
     typedef Io<T> IO;
