@@ -464,6 +464,52 @@ def leg_adjoint(torch, lib, fields, synth, n=256, nt=1000, ckpt=32):
 
 
 
+# The paper's own timings of this kernel (inner region of its Acoustic ISO
+# kernel, 750 x 994 x 300 grid, 10,000 iterations, "Kernel" column of the
+# CSL time-measurement table in its evaluation of runtime performance), in
+# seconds, with the device each ran on.  Context only: other hardware.
+PAPER_KERNEL_S = {"NVIDIA H100, CUDA f4 template": 45.0160, "AMD MI210, HIP gmem template": 138.1122,
+                  "Cerebras CS-2, CSL": 0.4685, "AMD EPYC 9684X (192 cores), OpenMP loop": 269.4177}
+
+
+def leg_paper(torch, lib, fields, synth, nt=10000):
+    """The paper's timing workload on this GPU: the leapfrog (inner region,
+    zero Dirichlet frame) on a 750 x 994 x 300 grid for 10,000 iterations,
+    FP32, layered model and Ricker source at the centre as in the headline
+    workload; kernel time from HIP events around the whole run, next to the
+    paper's own kernel times on its hardware."""
+    nx, ny, nz = 750, 994, 300
+    g = lib.grid_init(nx, ny, nz)
+    v = synth.layered_velocity(nx, ny, nz, 0)
+    dx = 10.0
+    dt = synth.cfl_dt(v, dx)
+    V = fields.Field(g).set_interior(v)
+    del v
+    amp = torch.tensor(synth.ricker(nt, dt, 15.0)[:, None], dtype=torch.float32, device="cuda")
+    src = lib.make_sources([[nx // 2, ny // 2, nz // 2]], amp.data_ptr(), 1)
+    co = lib.coeffs(synth.star25_coeffs())
+    ws = fields.WaveState(g)
+    stream = torch.cuda.current_stream()
+    lib.sp_wave_step(g, co, dt, dx, g, V.ptr, ws.st, 200, src=src, stream=stream)   # warm-up
+    ws.reset()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    lib.sp_wave_step(g, co, dt, dx, g, V.ptr, ws.st, nt, src=src, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3
+    finite = bool(torch.isfinite(ws.cur().interior()).all())
+    pts = nx * ny * nz * nt
+    out = {"config": "750x994x300, %d leapfrog iterations, FP32, layered v seed 0, Ricker 15 Hz at centre" % nt,
+           "kernel_s": round(t, 4), "gpts": round(pts / t / 1e9, 2),
+           "hbm_frac_at_16B": round(16 * pts / t / 1e9 / HBM_PEAK_GBS, 4), "finite": finite,
+           "paper_kernel_s": PAPER_KERNEL_S,
+           "paper_gpts": {k: round(pts / s / 1e9, 2) for k, s in PAPER_KERNEL_S.items()}}
+    del ws, V
+    return out
+
+
 def leg_fused(torch, lib, fields, synth, nt=100):
     """Two leapfrog steps per sweep (sp_wave_step_fused) against the
     single-step sweep on the 1024x1024x512 workload, nt steps each after a
@@ -701,7 +747,7 @@ def main():
                     help="override the headline grid (profiling runs only)")
     ap.add_argument("--no-headline", action="store_true",
                     help="skip the headline run (profiling runs of the extra legs)")
-    ap.add_argument("--legs", default="storage,storage_error,storage_oracle,adjoint,fused,pml,suite,serve",
+    ap.add_argument("--legs", default="storage,storage_error,storage_oracle,adjoint,paper,fused,pml,suite,serve",
                     help="extra measurements after the headline run (comma list; '' for none)")
     ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
                     help="instead of the benchmark, copy a GIB-sized buffer 4 times with torch "
@@ -838,6 +884,10 @@ def main():
     if "adjoint" in legs:
         log("adjoint gradient at 256^3")
         forms["adjoint_256"] = leg_adjoint(torch, lib, fields, synth)
+    if "paper" in legs:
+        log("the paper's timing workload")
+        forms["paper_workload"] = leg_paper(torch, lib, fields, synth)
+        torch.cuda.empty_cache()
     if "fused" in legs:
         log("two steps per sweep")
         forms["fused"] = leg_fused(torch, lib, fields, synth)
