@@ -210,19 +210,26 @@ __device__ __forceinline__ void star25_wave_raw16(const SweepArgs &a, const int 
     auto at = [](const char *base, uint32_t off) { return reinterpret_cast<const T *>(base + off); };
     auto vat = [](const char *base, uint32_t off) { return reinterpret_cast<const float *>(base + off); };
 
-    bool ld_ok[RY], st_ok[RY];
-    uint32_t own[RY], vown[RY];
+    // Every load takes a position clamped into the range that some lane
+    // really needs: the frame for u^n (queue and halo chunks), the interior
+    // for u^{n-1} and v.  A lane outside that range loads what an in-range
+    // lane loads; its values reach no stored output, so the loads need no
+    // per-lane predicate and no zero fill.
+    const int xl = min(x, ((a.nx + 3) >> 2) << 2);   // last vector inside the frame
+    const int xs = min(x, ((a.nx - 1) >> 2) << 2);   // last vector inside the interior
+    bool st_ok[RY];
+    uint32_t lown[RY], own[RY], vown[RY];
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
         const int y = ybase + j;
-        ld_ok[j] = (y < a.ny + 4) && (x < a.nx + 4);
+        const int yl = min(y, a.ny + 3), ys = min(y, a.ny - 1);
         st_ok[j] = (y < a.ny) && (x < a.nx);
-        own[j] = (uint32_t)(((int64_t)(y + 4) * a.sy + x + 4) * (int64_t)sizeof(T));
-        vown[j] = (uint32_t)(((int64_t)(y + 4) * a.vsy + x + 4) * 4);
+        lown[j] = (uint32_t)(((int64_t)(yl + 4) * a.sy + xl + 4) * (int64_t)sizeof(T));
+        own[j] = (uint32_t)(((int64_t)(ys + 4) * a.sy + xs + 4) * (int64_t)sizeof(T));
+        vown[j] = (uint32_t)(((int64_t)(ys + 4) * a.vsy + xs + 4) * 4);
     }
 
     int hrow[HPT], hchk[HPT];
-    bool h_ok[HPT];
     uint32_t hoff[HPT];
 #pragma unroll
     for (int j = 0; j < HPT; ++j) {
@@ -243,12 +250,9 @@ __device__ __forceinline__ void star25_wave_raw16(const SweepArgs &a, const int 
             hrow[j] = rr + 4;
             hchk[j] = side ? LX + 1 : 0;
         }
-        h_ok[j] = (k < HC) && (y0 + dy < a.ny + 4) && (x0 + dx < a.nx + 4);
-        hoff[j] = (uint32_t)(((int64_t)(y0 + dy + 4) * a.sy + x0 + dx + 4) * (int64_t)sizeof(T));
+        const int yh = min(y0 + dy, a.ny + 3), xh = min(x0 + dx, ((a.nx + 3) >> 2) << 2);
+        hoff[j] = (uint32_t)(((int64_t)(yh + 4) * a.sy + xh + 4) * (int64_t)sizeof(T));
     }
-
-    const f4v zero = {0.f, 0.f, 0.f, 0.f};
-    const raw rzero = IO::enc(zero, 1.f);
 
     __shared__ float s_in[MAX_BLOCK_SLABS], s_pv[MAX_BLOCK_SLABS], s_o[MAX_BLOCK_SLABS];
     const int ks = clampi((zb - 4) >> 4, 0, nslab - 1);
@@ -275,17 +279,17 @@ __device__ __forceinline__ void star25_wave_raw16(const SweepArgs &a, const int 
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const int zz = zb - 4 + i;
-            q[j][i] = ld_ok[j] ? IO::ld(at(plane(u, zz), own[j])) : rzero;
+            q[j][i] = IO::ld(at(plane(u, zz), lown[j]));
         }
-        nq[j] = ld_ok[j] ? IO::ld(at(plane(u, zb + 4), own[j])) : rzero;
+        nq[j] = IO::ld(at(plane(u, zb + 4), lown[j]));
     }
     // Halo chunks of planes z .. z+HQR-1.  The FP32 sweeps fetch them 5
     // planes ahead, when their owners fetch the same rows (L2 reuse); the
-    // raw 16-bit body keeps a shallower queue for occupancy: with depth 1
-    // the BF16 body fits three waves per SIMD (162 VGPRs, against 178 at
-    // depth 5), and FP16 at depth 2 keeps three (154).  Measured side by
-    // side on MI355X, 128x16x2 tiles: BF16 485 against 429 GPts/s at 512^3
-    // and 491 against 470 at 1024x1024x512; FP16 498 against 493 and 499
+    // raw 16-bit body keeps a shallower queue for occupancy: at depth 5
+    // the BF16 body needs 178 VGPRs (two waves per SIMD), at depth 1 it
+    // fits three, and FP16 keeps three at depth 2.  Measured side by side
+    // on MI355X, 128x16x2 tiles: BF16 485 against 429 GPts/s at 512^3 and
+    // 491 against 470 at 1024x1024x512; FP16 498 against 493 and 499
     // against 499.
     constexpr int HQR = std::is_same<T, __bf16>::value ? 1 : 2;
     raw hq[HPT][HQR];
@@ -293,7 +297,7 @@ __device__ __forceinline__ void star25_wave_raw16(const SweepArgs &a, const int 
     for (int j = 0; j < HPT; ++j)
 #pragma unroll
         for (int k = 0; k < HQR; ++k)
-            hq[j][k] = h_ok[j] ? IO::ld(at(plane(u, zb + k), hoff[j])) : rzero;
+            hq[j][k] = IO::ld(at(plane(u, zb + k), hoff[j]));
 
     // u^{n-1} and v one plane ahead (two planes ahead measured 2-3 % slower:
     // the extra registers cost BF16 its third wave per SIMD)
@@ -301,12 +305,8 @@ __device__ __forceinline__ void star25_wave_raw16(const SweepArgs &a, const int 
     f4v vv[RY];
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
-        pp[j] = rzero;
-        vv[j] = zero;
-        if (st_ok[j]) {
-            pp[j] = IO::ld_nt(at(plane(uprev, zb), own[j]));
-            vv[j] = ld4_nt(vat(vplane(zb), vown[j]));
-        }
+        pp[j] = IO::ld_nt(at(plane(uprev, zb), own[j]));
+        vv[j] = ld4_nt(vat(vplane(zb), vown[j]));
     }
 
     // this step's source amplitudes, read once per block
@@ -319,7 +319,11 @@ __device__ __forceinline__ void star25_wave_raw16(const SweepArgs &a, const int 
     float tmax = 0.f;
     bool bad = false;                     // a non-finite output seen by this lane
 
-    for (int z = zb; z < ze; ++z) {
+    // One plane of the chunk; MORE: issue the next plane's loads and advance
+    // the queues (every plane but the chunk's last, which is peeled off the
+    // loop so that no load needs a predicate).
+    auto sweep_plane = [&](const int z, auto more) {
+        constexpr bool MORE = decltype(more)::value;
         const int b = z & 1;
         if (z == zb || (z & (SP_SLAB - 1)) == 0) {
             s_out = s_o[slab_of(z)];
@@ -335,28 +339,18 @@ __device__ __forceinline__ void star25_wave_raw16(const SweepArgs &a, const int 
             if (tid + j * NT < HC) lds[b][hrow[j]][hchk[j]] = hq[j][0];
 
         raw hn[HPT];
-#pragma unroll
-        for (int j = 0; j < HPT; ++j) hn[j] = rzero;
         raw pp_n[RY];
         f4v vv_n[RY];
+        if constexpr (MORE) {
 #pragma unroll
-        for (int j = 0; j < RY; ++j) {
-            pp_n[j] = rzero;
-            vv_n[j] = zero;
-        }
-        if (z + 1 < ze) {
+            for (int j = 0; j < RY; ++j) nq[j] = IO::ld(at(plane(u, z + 5), lown[j]));
 #pragma unroll
-            for (int j = 0; j < RY; ++j)
-                nq[j] = ld_ok[j] ? IO::ld(at(plane(u, z + 5), own[j])) : rzero;
+            for (int j = 0; j < HPT; ++j) hn[j] = IO::ld(at(plane(u, z + HQR), hoff[j]));
 #pragma unroll
-            for (int j = 0; j < HPT; ++j)
-                hn[j] = h_ok[j] ? IO::ld(at(plane(u, z + HQR), hoff[j])) : rzero;
-#pragma unroll
-            for (int j = 0; j < RY; ++j)
-                if (st_ok[j]) {
-                    pp_n[j] = IO::ld_nt(at(plane(uprev, z + 1), own[j]));
-                    vv_n[j] = ld4_nt(vat(vplane(z + 1), vown[j]));
-                }
+            for (int j = 0; j < RY; ++j) {
+                pp_n[j] = IO::ld_nt(at(plane(uprev, z + 1), own[j]));
+                vv_n[j] = ld4_nt(vat(vplane(z + 1), vown[j]));
+            }
         }
 
         lds_barrier();
@@ -453,20 +447,24 @@ __device__ __forceinline__ void star25_wave_raw16(const SweepArgs &a, const int 
             tmax = 0.f;
         }
 
+        if constexpr (MORE) {
 #pragma unroll
-        for (int j = 0; j < RY; ++j) {
+            for (int j = 0; j < RY; ++j) {
 #pragma unroll
-            for (int i = 0; i < 8; ++i) q[j][i] = q[j][i + 1];
-            pp[j] = pp_n[j];
-            vv[j] = vv_n[j];
+                for (int i = 0; i < 8; ++i) q[j][i] = q[j][i + 1];
+                pp[j] = pp_n[j];
+                vv[j] = vv_n[j];
+            }
+#pragma unroll
+            for (int j = 0; j < HPT; ++j) {
+#pragma unroll
+                for (int k = 0; k + 1 < HQR; ++k) hq[j][k] = hq[j][k + 1];
+                hq[j][HQR - 1] = hn[j];
+            }
         }
-#pragma unroll
-        for (int j = 0; j < HPT; ++j) {
-#pragma unroll
-            for (int k = 0; k + 1 < HQR; ++k) hq[j][k] = hq[j][k + 1];
-            hq[j][HQR - 1] = hn[j];
-        }
-    }
+    };
+    for (int z = zb; z + 1 < ze; ++z) sweep_plane(z, std::true_type());
+    sweep_plane(ze - 1, std::false_type());
     if (NF) report_nonfinite(a.nonfinite, bad);
 }
 
@@ -1043,8 +1041,19 @@ __device__ __forceinline__ void star25_body(const SweepArgs &a, const int lin) {
     }
 }
 
+// Register cap of a kernel instance: the 16-bit leapfrog on its default
+// 128x16x2 tiles is held to 168 VGPRs, three waves per SIMD.  Left alone the
+// compiler takes 170-180 and drops to two waves (served batches: 342
+// against 372 GPts/s, measured); at the cap the batched form spills a few
+// bytes outside its plane loop.  The other instances take what they need.
+template <int TX, int TY, int RY, int MODE, typename T>
+constexpr int waves_per_simd() {
+    return Io<T>::scaled && MODE == MODE_WAVE && TX == 128 && TY == 16 && RY == 2 ? 3 : 1;
+}
+
 template <int TX, int TY, int RY, int MODE, typename T>
 __global__ void __launch_bounds__((TX / 4) * (TY / RY))
+__attribute__((amdgpu_waves_per_eu(waves_per_simd<TX, TY, RY, MODE, T>())))
 k_star25(SweepArgs a) {
     star25_body<TX, TY, RY, MODE, T>(a, xcd_tile(blockIdx.x, gridDim.x));
 }
@@ -1073,6 +1082,7 @@ __global__ void __launch_bounds__(512) k_star25_shell(const BoxSet bs) {
 // XCD receives contiguous tiles of the same grid.
 template <int TX, int TY, int RY, int MODE, typename T>
 __global__ void __launch_bounds__((TX / 4) * (TY / RY))
+__attribute__((amdgpu_waves_per_eu(waves_per_simd<TX, TY, RY, MODE, T>())))
 k_star25_batch(const SweepArgs *__restrict__ args, const int2 *__restrict__ table) {
     const int2 e = table[blockIdx.x];
     star25_body<TX, TY, RY, MODE, T, true>(args[e.x], e.y);
