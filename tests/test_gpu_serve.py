@@ -99,9 +99,11 @@ def test_late_requests_join_running_batch(gpu_lib):
     from paper_2309_04671_amd import lib, serve
     cl = serve.ServeClient(arena_bytes=2 << 30, max_slots=8, chunk_steps=8)
     first = _shots(serve, lib, [(384, 384, 256, 0, 2000)])[0][1]      # ~0.2 s of work
+    # the late requests are built beforehand, so that nothing but the
+    # sleep separates their submission from the first one's
+    late = [s for _, s in _shots(serve, lib, [(96, 96, 64, 1, 40), (64, 64, 64, 0, 30)])]
     cl.submit(first)
     time.sleep(0.02)
-    late = [s for _, s in _shots(serve, lib, [(96, 96, 64, 1, 40), (64, 64, 64, 0, 30)])]
     for s in late:
         cl.submit(s)
     cl.drain()
