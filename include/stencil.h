@@ -17,7 +17,8 @@
  *    enqueued; sp_last_error() returns a thread-local message.
  *  - Every data pointer is a DEVICE pointer owned by the caller, unless the
  *    comment says HOST.  The library never allocates device memory outside
- *    a caller-provided workspace.
+ *    a caller-provided workspace or arena; sp_energy_noalloc instead uses a
+ *    static per-device array that is part of the loaded library.
  *  - `stream` is a hipStream_t passed as void* (NULL = default stream).  All
  *    compute calls are asynchronous on that stream; a device fault surfaces at
  *    the next synchronisation.
