@@ -100,6 +100,45 @@ def test_single_step_parity(gpu_lib, fmt, tile, monkeypatch):
     assert e["rel_l2"] <= (2.0 ** -11 if fmt == "f16" else 2.0 ** -8)
 
 
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (3, 5, 2), (5, 1, 17), (2, 19, 3), (7, 3, 33), (66, 2, 16)])
+@pytest.mark.parametrize("fmt", ["f16", "bf16"])
+def test_single_step_degenerate_shapes(gpu_lib, fmt, shape):
+    # Grids thinner than a tile or a load vector in some direction, where
+    # most lanes load from clamped positions: one step from a random stored
+    # state against the storage emulation, with a source at the centre.
+    from paper_2309_04671_amd import fields, lib
+    nx, ny, nz = shape
+    g = lib.grid_init(nx, ny, nz, FMT[fmt])
+    gv = lib.grid_init(nx, ny, nz)
+    v = synth.layered_velocity(nx, ny, nz, 5)
+    V = fields.Field(gv).set_interior(v)
+    dx = 10.0
+    dt = synth.cfl_dt(v, dx)
+    co = synth.star25_coeffs()
+    rng = np.random.default_rng(nx * 10007 + ny * 101 + nz)
+    n = lowp.nslab(nz)
+    s_cur = (2.0 ** rng.integers(-30, -10, n)).astype(np.float32)
+    s_prev = (s_cur * 2).astype(np.float32)
+    q_cur = lowp.round_to(rng.uniform(-2.0 ** 12, 2.0 ** 12, (nz, ny, nx)), fmt)
+    q_prev = lowp.round_to(rng.uniform(-2.0 ** 12, 2.0 ** 12, (nz, ny, nx)), fmt)
+    ws = _state_from(fields, g, q_prev, s_prev, q_cur, s_cur, fmt)
+    src_xyz = np.array([[nx // 2, ny // 2, nz // 2]], np.int32)
+    amp = torch.tensor([[1.0e-2]], dtype=torch.float32, device="cuda")
+    lib.sp_wave_step(g, lib.coeffs(co), dt, dx, gv, V.ptr, ws.st, 1,
+                     src=lib.make_sources(src_xyz, amp.data_ptr(), 1))
+    torch.cuda.synchronize()
+    q_gpu = ws.cur().get_interior().astype(np.float64)
+    s_gpu = ws.slot(1)[0].cpu().numpy()
+    a_gpu = ws.slot(1)[1].cpu().numpy()
+    q_ref, s_ref, _, _ = lowp.step(co, v, dt, dx, fmt, q_prev, s_prev, lowp.slab_amax(q_prev, s_prev),
+                                   q_cur, s_cur, lowp.slab_amax(q_cur, s_cur), src=src_xyz,
+                                   amp_row=amp[0].cpu().numpy())
+    assert np.array_equal(s_gpu, s_ref), shape
+    d = np.abs(q_gpu - q_ref)
+    assert np.all(d <= lowp.ulp(q_ref, fmt) + 2.0 ** -4), (shape, float(np.max(d)))
+    assert np.array_equal(a_gpu, lowp.slab_amax(q_gpu, s_gpu)), shape
+
 @pytest.mark.parametrize("fmt", ["f16", "bf16"])
 def test_multi_step_with_receivers(gpu_lib, fmt):
     from paper_2309_04671_amd import fields, lib
