@@ -70,8 +70,12 @@ int check_grid(const sp_grid *g, const char *what, bool allow_2d = false) {
     if (flat && !allow_2d) return fail(SP_EINVAL, "%s: 2D grids are not accepted here", what);
     const int rc = flat ? sp_grid_init_2d(g->nx, g->ny, g->halo, g->dtype, &ref)
                         : sp_grid_init(g->nx, g->ny, g->nz, g->halo, g->dtype, &ref);
-    if (rc != SP_OK)
-        return fail(SP_EINVAL, "%s: invalid grid descriptor (%s)", what, sp_last_error());
+    if (rc != SP_OK) {
+        // the message lives in the buffer that fail() writes: copy it first
+        char why[sizeof g_err];
+        std::snprintf(why, sizeof why, "%s", g_err);
+        return fail(SP_EINVAL, "%s: invalid grid descriptor (%s)", what, why);
+    }
     if (std::memcmp(&ref, g, sizeof ref) != 0)
         return fail(SP_EINVAL, "%s: grid descriptor was not produced by sp_grid_init", what);
     return SP_OK;

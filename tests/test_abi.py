@@ -82,6 +82,13 @@ def test_apply_validates_before_launch():
     rc = L.sp_stencil_apply(ctypes.byref(bad), ctypes.byref(c), 1, ctypes.c_void_p(1 << 30),
                             ctypes.c_void_p(1 << 40), ctypes.byref(out), None)
     assert rc == lib.SP_EINVAL and "sp_grid_init" in lib.last_error()
+    # a descriptor whose own dimensions are invalid: the message keeps the reason
+    bad = lib.grid_init(16, 16, 16)
+    bad.halo = 3
+    rc = L.sp_stencil_apply(ctypes.byref(bad), ctypes.byref(c), 1, ctypes.c_void_p(1 << 30),
+                            ctypes.c_void_p(1 << 40), ctypes.byref(out), None)
+    msg = lib.last_error()
+    assert rc == lib.SP_EINVAL and "invalid grid descriptor" in msg and "halo" in msg, msg
     # FP16 grids are not supported by apply
     h = lib.grid_init(16, 16, 16, lib.SP_F16)
     rc = L.sp_stencil_apply(ctypes.byref(h), ctypes.byref(c), 1, ctypes.c_void_p(1 << 30),
