@@ -13,8 +13,12 @@
  *
  * Conventions shared by every call
  * --------------------------------
- *  - Return value: SP_OK (0) or an SP_E* code.  On error nothing has been
- *    enqueued; sp_last_error() returns a thread-local message.
+ *  - Return value: SP_OK (0) or an SP_E* code; sp_last_error() returns a
+ *    thread-local message.  Arguments are validated before anything is
+ *    enqueued, so an SP_EINVAL / SP_EUNSUPPORTED / SP_ENOMEM return leaves
+ *    every buffer and state untouched.  SP_EDEVICE from a failed launch
+ *    part-way through a multi-step call leaves the state (pointers and step
+ *    counter) at the last step that was enqueued.
  *  - Every data pointer is a DEVICE pointer owned by the caller, unless the
  *    comment says HOST.  The library never allocates device memory outside
  *    a caller-provided workspace or arena; sp_energy_noalloc instead uses a

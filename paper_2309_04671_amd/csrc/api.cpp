@@ -81,10 +81,13 @@ int check_grid(const sp_grid *g, const char *what, bool allow_2d = false) {
     return SP_OK;
 }
 
-bool overlaps(const void *a, const void *b, int64_t bytes) {
+// Do [a, a + abytes) and [b, b + bbytes) intersect?
+bool overlaps(const void *a, int64_t abytes, const void *b, int64_t bbytes) {
     const auto x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
-    return x < y + (uintptr_t)bytes && y < x + (uintptr_t)bytes;
+    return x < y + (uintptr_t)bbytes && y < x + (uintptr_t)abytes;
 }
+
+bool overlaps(const void *a, const void *b, int64_t bytes) { return overlaps(a, bytes, b, bytes); }
 
 sp::StarCoef to_f32(const sp_coeffs *c) {
     sp::StarCoef s;
@@ -381,7 +384,7 @@ int sp_wave_step(const sp_grid *g, const sp_coeffs *c, double dt, double dx, con
     if (!aligned16(st->cur) || !aligned16(st->prev))
         return fail(SP_EINVAL, "sp_wave_step: pointers must be 16-byte aligned");
     if (overlaps(st->cur, st->prev, g->bytes)) return fail(SP_EINVAL, "sp_wave_step: cur and prev overlap");
-    if (overlaps(st->cur, v, g->bytes) || overlaps(st->prev, v, g->bytes))
+    if (overlaps(st->cur, g->bytes, v, gv->bytes) || overlaps(st->prev, g->bytes, v, gv->bytes))
         return fail(SP_EINVAL, "sp_wave_step: v overlaps a wavefield");
     if (st->step < 0) return fail(SP_EINVAL, "sp_wave_step: negative step counter");
     const int nsrc = a.src.n;

@@ -130,6 +130,12 @@ def test_wave_step_validates_before_launch():
     assert call(rec=rec) == lib.SP_EINVAL
     # the state must be untouched by a rejected call
     assert st.cur == 1 << 30 and st.step == 0
+    # a 16-bit wavefield placed in the upper part of the (larger) FP32 v
+    h, hv = lib.grid_init(256, 8, 8, lib.SP_F16), lib.grid_init(256, 8, 8)
+    inside = (1 << 40) + h.bytes                  # past v's first h.bytes, inside v
+    hs = lib.sp_wave_state(inside, 1 << 36, 1 << 20, 0)
+    assert h.bytes < hv.bytes
+    assert call(g=h, gv=hv, st=hs) == lib.SP_EINVAL and "v overlaps" in lib.last_error()
 
 
 def test_fused_step_validates_before_launch(monkeypatch):
