@@ -78,6 +78,7 @@ class ServeClient:
         t = ctypes.c_uint64()
         lib.check(lib.load().sp_submit(self.q, ctypes.byref(shot.desc), ctypes.byref(t)))
         shot.ticket = t.value
+        # the queue holds raw pointers into the shot's buffers until it finishes
         self.shots[t.value] = shot
         return t.value
 
@@ -86,7 +87,10 @@ class ServeClient:
         rc = lib.load().sp_poll(self.q, ctypes.c_uint64(ticket), ctypes.byref(st))
         if rc not in (lib.SP_OK, lib.SP_EPENDING):
             lib.check(rc)
-        return rc == lib.SP_OK, st
+        done = rc == lib.SP_OK
+        if done:
+            self.shots.pop(ticket, None)    # finished: the queue no longer uses its buffers
+        return done, st
 
     def drain(self):
         lib.check(lib.load().sp_queue_drain(self.q))
@@ -95,6 +99,7 @@ class ServeClient:
         if self.q:
             lib.check(lib.load().sp_queue_destroy(self.q))
             self.q = ctypes.c_void_p()
+        self.shots.clear()
 
     def __del__(self):
         try:
