@@ -1336,11 +1336,11 @@ TileCfg choose_tiles(int nx, int ny, int nz, int dtype, int mode) {
     // side per row) and the y-halo rows small relative to the tile, and two
     // rows per thread share their y-neighbour reads.  The candidates depend
     // on the storage type, because what limits each kernel differs:
-    //  * FP32 (184 VGPRs, 16-byte accesses): 512-thread 256x16x2 tiles, one
+    //  * FP32 (231 VGPRs, 16-byte accesses): 512-thread 256x16x2 tiles, one
     //    block per CU, z split only when there are fewer than 256 tiles
     //    (the leapfrog on grids that need 16-plane chunks: 256x16x1);
-    //  * FP16 and BF16 (the raw 16-bit body: about 165 and 181 VGPRs,
-    //    8-byte accesses, latency-bound): 256-thread 128x16x2 tiles and many
+    //  * FP16 and BF16 (the raw 16-bit body, held to 168 VGPRs for three
+    //    waves per SIMD, 8-byte accesses): 256-thread 128x16x2 tiles and many
     //    short z-chunks (about 4096 blocks) so that the CUs stay evenly
     //    loaded (BF16 at 512^3: 453 GPts/s against 345 on the 1024-thread
     //    256x16x1 tiles the decoding body had used);
@@ -1357,7 +1357,8 @@ TileCfg choose_tiles(int nx, int ny, int nz, int dtype, int mode) {
     //    plus backward: 0.220 s against 0.224 on 256x8x1 and 0.233 on
     //    64x16x1 tiles);
     // z-chunks are at least 16 planes (each chunk re-reads 8 planes of u,
-    // mostly from L2).  These targets are measured optima on MI355X.
+    // mostly from L2) unless the grid is too small to fill the GPU (see
+    // occupancy_zchunk).  These targets are measured optima on MI355X.
     struct Cand {
         int tx, ty, ry, want, min_tiles_x;
     };
