@@ -165,7 +165,8 @@ int sp_apply(const sp_grid *g, const sp_stencil *s, int sweeps, void *u, void *v
  * chooses s_k of u^{n+1} before computing it:
  *     B_k = 8 max(amax(u^n) slabs k-1..k+1, amax(u^{n-1}) slab k)
  *           + sum over sources in slab k of |dt^2 v^2 amp|  (FP32),
- *     s_k = 2^(ceil(log2 B_k) - 15)  (1 if B_k = 0),
+ *     s_k = 2^(ceil(log2 B_k) - 15)  (1 if B_k = 0; the exponent clamped
+ *           to [-110, 110], so s_k and 1/s_k stay normal FP32 numbers),
  * which keeps |q| <= 2^15 inside the stability limit; values are rounded to
  * nearest even.  Halo planes are decoded with the nearest slab's scale.
  */
