@@ -101,6 +101,40 @@ def test_single_step_parity(gpu_lib, fmt, tile, monkeypatch):
 
 
 
+
+@pytest.mark.parametrize("fmt", ["f16", "bf16"])
+def test_scale_exponent_clamp(gpu_lib, fmt):
+    # A field of magnitude ~2^-100: the next scales' exponent ceil(log2 B) - 15
+    # falls below -110 and is clamped there on both sides; the stored values
+    # still follow the emulation.
+    from paper_2309_04671_amd import fields, lib
+    nx, ny, nz = 40, 24, 40
+    g = lib.grid_init(nx, ny, nz, FMT[fmt])
+    gv = lib.grid_init(nx, ny, nz)
+    v = synth.layered_velocity(nx, ny, nz, 2)
+    V = fields.Field(gv).set_interior(v)
+    dx = 10.0
+    dt = synth.cfl_dt(v, dx)
+    co = synth.star25_coeffs()
+    rng = np.random.default_rng(110)
+    n = lowp.nslab(nz)
+    s_cur = np.full(n, 2.0 ** -110, np.float32)
+    s_prev = s_cur.copy()
+    q_cur = lowp.round_to(rng.uniform(-2.0 ** 10, 2.0 ** 10, (nz, ny, nx)), fmt)
+    q_prev = lowp.round_to(rng.uniform(-2.0 ** 10, 2.0 ** 10, (nz, ny, nx)), fmt)
+    ws = _state_from(fields, g, q_prev, s_prev, q_cur, s_cur, fmt)
+    lib.sp_wave_step(g, lib.coeffs(co), dt, dx, gv, V.ptr, ws.st, 1)
+    torch.cuda.synchronize()
+    q_gpu = ws.cur().get_interior().astype(np.float64)
+    s_gpu = ws.slot(1)[0].cpu().numpy()
+    q_ref, s_ref, _, _ = lowp.step(co, v, dt, dx, fmt, q_prev, s_prev, lowp.slab_amax(q_prev, s_prev),
+                                   q_cur, s_cur, lowp.slab_amax(q_cur, s_cur))
+    assert np.all(s_ref == np.float32(2.0 ** -110))
+    assert np.array_equal(s_gpu, s_ref)
+    assert np.all(np.isfinite(q_gpu))
+    d = np.abs(q_gpu - q_ref)
+    assert np.all(d <= lowp.ulp(q_ref, fmt) + 2.0 ** -4), float(np.max(d))
+
 @pytest.mark.parametrize("shape", [(1, 1, 1), (3, 5, 2), (5, 1, 17), (2, 19, 3), (7, 3, 33), (66, 2, 16)])
 @pytest.mark.parametrize("fmt", ["f16", "bf16"])
 def test_single_step_degenerate_shapes(gpu_lib, fmt, shape):

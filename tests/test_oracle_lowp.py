@@ -73,6 +73,21 @@ def test_scale_rule_exponents():
     assert list(s) == [1.0, 2.0 ** -13, 1.0]
 
 
+def test_scale_rule_exponent_is_clamped():
+    # tiny and huge slab maxima: e = ceil(log2 B) - 15 is clamped to
+    # [-110, 110], so the scale and its reciprocal stay normal FP32 numbers
+    a_cur = np.array([2.0 ** -100, 2.0 ** -98, 2.0 ** 100, 2.0 ** 124], np.float32)
+    s = lowp.next_scales(a_cur, np.zeros(4, np.float32), 64, 1.0, None, None, None)
+    # slab 0: B = 8 max(2^-100, 2^-98) = 2^-95 -> e = -110 (exactly the bound)
+    # slab 1: B = 8 * 2^100 = 2^103 -> e = 88
+    # slabs 2, 3: B = 8 * 2^124 = 2^127 -> e = 112, clamped to 110
+    assert list(s) == [2.0 ** -110, 2.0 ** 88, 2.0 ** 110, 2.0 ** 110]
+    s = lowp.next_scales(np.array([2.0 ** -120], np.float32), np.zeros(1, np.float32), 16, 1.0,
+                         None, None, None)
+    assert list(s) == [2.0 ** -110]          # 2^-117 - 15 = -132 -> -110
+    assert np.isfinite(1.0 / s).all() and (s >= np.finfo(np.float32).tiny).all()
+
+
 @pytest.mark.parametrize("fmt", ["f16", "bf16"])
 def test_step_keeps_stored_values_in_range(fmt):
     # Worst-case growth inside the stability limit: |q_next| <= 2^15.
