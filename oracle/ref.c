@@ -28,6 +28,28 @@
 
 #define H 4
 
+/* Allocation that stops with a message instead of returning NULL (the
+ * full-size checks allocate several GB per field). */
+static void *xcalloc(size_t n, size_t size)
+{
+    void *p = calloc(n, size);
+    if (!p && n && size) {
+        fprintf(stderr, "oracle: cannot allocate %zu x %zu bytes\n", n, size);
+        abort();
+    }
+    return p;
+}
+
+static void *xmalloc(size_t size)
+{
+    void *p = malloc(size);
+    if (!p && size) {
+        fprintf(stderr, "oracle: cannot allocate %zu bytes\n", size);
+        abort();
+    }
+    return p;
+}
+
 /* Progress lines on stderr every `progress_every` time steps of the long
  * runs (0: none).  Reporting only; no result depends on it. */
 static int progress_every = 0;
@@ -110,7 +132,7 @@ void ref_wave_run(int nx, int ny, int nz, const double *c, double dt, double dx,
                   double *prev, double *cur)
 {
     const int64_t np = padded_count(nx, ny, nz);
-    double *lap = (double *)calloc((size_t)np, sizeof(double));
+    double *lap = (double *)xcalloc((size_t)np, sizeof(double));
     double *bufs[2] = {prev, cur};
     int ip = 0, ic = 1;
     const double r = dt / dx;
@@ -140,7 +162,7 @@ void ref_wave_run(int nx, int ny, int nz, const double *c, double dt, double dx,
     }
     /* the newest state is bufs[ic]; put u^N in cur and u^{N-1} in prev */
     if (bufs[ic] != cur) {
-        double *tmp = (double *)malloc((size_t)np * sizeof(double));
+        double *tmp = (double *)xmalloc((size_t)np * sizeof(double));
         memcpy(tmp, cur, (size_t)np * sizeof(double));
         memcpy(cur, prev, (size_t)np * sizeof(double));
         memcpy(prev, tmp, (size_t)np * sizeof(double));
@@ -158,7 +180,7 @@ void ref_wave_run(int nx, int ny, int nz, const double *c, double dt, double dx,
 double ref_energy(int nx, int ny, int nz, const double *c, double dt, double dx,
                   const double *v, const double *u0, const double *u1)
 {
-    double *part = (double *)calloc((size_t)nz, sizeof(double));
+    double *part = (double *)xcalloc((size_t)nz, sizeof(double));
     const double r = dt / dx;
 #pragma omp parallel for schedule(static)
     for (int z = 0; z < nz; ++z) {
@@ -189,7 +211,7 @@ double ref_energy(int nx, int ny, int nz, const double *c, double dt, double dx,
 static double *wave_m(int nx, int ny, int nz, double dt, double dx, const double *v)
 {
     const double r = dt / dx;
-    double *m = (double *)calloc((size_t)padded_count(nx, ny, nz), sizeof(double));
+    double *m = (double *)xcalloc((size_t)padded_count(nx, ny, nz), sizeof(double));
 #pragma omp parallel for schedule(static)
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y)
@@ -295,13 +317,13 @@ double ref_adjoint_grad(int nx, int ny, int nz, const double *c, double dt, doub
     const int N = nsteps;
     double *m = wave_m(nx, ny, nz, dt, dx, v);
     /* all states u^{-1}..u^N: u[n+1] is u^n */
-    double *u = (double *)calloc((size_t)np * (N + 2), sizeof(double));
-    double *lap = (double *)calloc((size_t)np, sizeof(double));
+    double *u = (double *)xcalloc((size_t)np * (N + 2), sizeof(double));
+    double *lap = (double *)xcalloc((size_t)np, sizeof(double));
 #define U(n) (u + (int64_t)((n) + 1) * np)
     for (int n = 0; n < N; ++n)
         fwd_step(nx, ny, nz, c, dx, m, U(n - 1), U(n), U(n + 1), lap, n, nsrc, src, amp);
     /* residuals and misfit */
-    double *res = (double *)calloc((size_t)N * (nrec > 0 ? nrec : 1), sizeof(double));
+    double *res = (double *)xcalloc((size_t)N * (nrec > 0 ? nrec : 1), sizeof(double));
     double J = 0.0;
     for (int k = 1; k <= N; ++k)
         for (int q = 0; q < nrec; ++q) {
@@ -311,11 +333,11 @@ double ref_adjoint_grad(int nx, int ny, int nz, const double *c, double dt, doub
             J += 0.5 * d * d;
         }
     /* adjoint sweep */
-    double *l1 = (double *)calloc((size_t)np, sizeof(double)); /* lambda^{k+1} */
-    double *l2 = (double *)calloc((size_t)np, sizeof(double)); /* lambda^{k+2} */
-    double *l0 = (double *)calloc((size_t)np, sizeof(double)); /* lambda^k     */
-    double *ml = (double *)calloc((size_t)np, sizeof(double));
-    double *gm = (double *)calloc((size_t)np, sizeof(double));
+    double *l1 = (double *)xcalloc((size_t)np, sizeof(double)); /* lambda^{k+1} */
+    double *l2 = (double *)xcalloc((size_t)np, sizeof(double)); /* lambda^{k+2} */
+    double *l0 = (double *)xcalloc((size_t)np, sizeof(double)); /* lambda^k     */
+    double *ml = (double *)xcalloc((size_t)np, sizeof(double));
+    double *gm = (double *)xcalloc((size_t)np, sizeof(double));
     for (int k = N; k >= 1; --k) {
         adj_step(nx, ny, nz, c, dx, m, l1, l2, l0, U(k - 1), gm, ml, lap, k, nsrc, src, amp,
                  nrec, rec, res);
@@ -352,12 +374,12 @@ double ref_adjoint_grad_ckpt(int nx, int ny, int nz, const double *c, double dt,
     const int C = ckpt < 1 ? 1 : ckpt;
     const int nseg = N > 0 ? (N + C - 1) / C : 0;
     double *m = wave_m(nx, ny, nz, dt, dx, v);
-    double *lap = (double *)calloc((size_t)np, sizeof(double));
+    double *lap = (double *)xcalloc((size_t)np, sizeof(double));
     /* segment-start pairs: pair[2j] = u^{jC-1}, pair[2j+1] = u^{jC} */
-    double *pair = (double *)calloc((size_t)np * 2 * (nseg > 0 ? nseg : 1), sizeof(double));
+    double *pair = (double *)xcalloc((size_t)np * 2 * (nseg > 0 ? nseg : 1), sizeof(double));
     /* segment ring: ring[i] = u^{n0-1+i}, i = 0..C */
-    double *ring = (double *)calloc((size_t)np * (C + 1), sizeof(double));
-    double *res = (double *)calloc((size_t)N * (nrec > 0 ? nrec : 1), sizeof(double));
+    double *ring = (double *)xcalloc((size_t)np * (C + 1), sizeof(double));
+    double *res = (double *)xcalloc((size_t)N * (nrec > 0 ? nrec : 1), sizeof(double));
 #define RING(i) (ring + (int64_t)(i) * np)
 #define PAIR(j, h) (pair + ((int64_t)2 * (j) + (h)) * np)
     /* forward pass from zero states: three rotating buffers in the ring */
@@ -366,7 +388,7 @@ double ref_adjoint_grad_ckpt(int nx, int ny, int nz, const double *c, double dt,
         double *b[3] = {RING(0), RING(1), RING(2 <= C ? 2 : 0)};
         double *extra = NULL;
         if (C < 2) {                    /* C = 1: the ring has two fields only */
-            extra = (double *)calloc((size_t)np, sizeof(double));
+            extra = (double *)xcalloc((size_t)np, sizeof(double));
             b[2] = extra;
         }
         double *up = b[0], *uc = b[1], *un = b[2];
@@ -389,11 +411,11 @@ double ref_adjoint_grad_ckpt(int nx, int ny, int nz, const double *c, double dt,
         free(extra);
     }
     /* adjoint pass, segments last to first */
-    double *l1 = (double *)calloc((size_t)np, sizeof(double)); /* lambda^{k+1} */
-    double *l2 = (double *)calloc((size_t)np, sizeof(double)); /* lambda^{k+2} */
-    double *l0 = (double *)calloc((size_t)np, sizeof(double)); /* lambda^k     */
-    double *ml = (double *)calloc((size_t)np, sizeof(double));
-    double *gm = (double *)calloc((size_t)np, sizeof(double));
+    double *l1 = (double *)xcalloc((size_t)np, sizeof(double)); /* lambda^{k+1} */
+    double *l2 = (double *)xcalloc((size_t)np, sizeof(double)); /* lambda^{k+2} */
+    double *l0 = (double *)xcalloc((size_t)np, sizeof(double)); /* lambda^k     */
+    double *ml = (double *)xcalloc((size_t)np, sizeof(double));
+    double *gm = (double *)xcalloc((size_t)np, sizeof(double));
     for (int j = nseg - 1; j >= 0; --j) {
         const int n0 = j * C;
         const int L = N - n0 < C ? N - n0 : C;
@@ -534,7 +556,7 @@ void ref_wave_pml_run(int nx, int ny, int nz, const double *c, double dt, double
                       double *prev, double *cur, double *psi)
 {
     const int64_t np = padded_count(nx, ny, nz);
-    double *lap = (double *)calloc((size_t)np, sizeof(double));
+    double *lap = (double *)xcalloc((size_t)np, sizeof(double));
     double *bufs[2] = {prev, cur};
     int ip = 0, ic = 1;
     const double r = dt / dx;
@@ -571,7 +593,7 @@ void ref_wave_pml_run(int nx, int ny, int nz, const double *c, double dt, double
         int t = ip; ip = ic; ic = t;
     }
     if (bufs[ic] != cur) {
-        double *tmp = (double *)malloc((size_t)np * sizeof(double));
+        double *tmp = (double *)xmalloc((size_t)np * sizeof(double));
         memcpy(tmp, cur, (size_t)np * sizeof(double));
         memcpy(cur, prev, (size_t)np * sizeof(double));
         memcpy(prev, tmp, (size_t)np * sizeof(double));
