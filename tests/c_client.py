@@ -26,8 +26,14 @@ def compile_client(out: str = BIN) -> str:
     return out
 
 
+def client_binary(scratch_dir: str) -> str:
+    """The client that build() made, or (if it is missing) one compiled now
+    into scratch_dir."""
+    if os.path.exists(BIN):
+        return BIN
+    return compile_client(os.path.join(scratch_dir, "abi_client"))
+
+
 def run_client(*args, binary: str = BIN, timeout: int = 120) -> subprocess.CompletedProcess:
-    if not os.path.exists(binary):
-        raise RuntimeError("the C client is not built: run __graft_entry__.build()")
     return subprocess.run([binary] + [str(a) for a in args], capture_output=True, text=True,
                           timeout=timeout)

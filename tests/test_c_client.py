@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 import synth
-from tests.c_client import ROOT, compile_client, run_client
+from tests.c_client import ROOT, client_binary, compile_client, run_client
 
 
 def _coeff_file(path, co):
@@ -42,7 +42,9 @@ def test_c_client_apply_matches_oracle(gpu_lib, tmp_path, shape):
     co = synth.integer_coeffs()
     u.astype(np.float32).tofile(tmp_path / "u.f32")
     _coeff_file(tmp_path / "c.f64", co)
-    r = run_client("apply", nx, ny, nz, 1, tmp_path / "u.f32", tmp_path / "c.f64", tmp_path / "out.f32")
+    exe = client_binary(str(tmp_path))
+    r = run_client("apply", nx, ny, nz, 1, tmp_path / "u.f32", tmp_path / "c.f64", tmp_path / "out.f32",
+                   binary=exe)
     assert r.returncode == 0, r.stderr
     assert "result in v" in r.stdout
     got = np.fromfile(tmp_path / "out.f32", np.float32).reshape(shape)
@@ -52,7 +54,8 @@ def test_c_client_apply_matches_oracle(gpu_lib, tmp_path, shape):
     co = synth.star25_coeffs()
     u.tofile(tmp_path / "u.f32")
     _coeff_file(tmp_path / "c.f64", co)
-    r = run_client("apply", nx, ny, nz, 2, tmp_path / "u.f32", tmp_path / "c.f64", tmp_path / "out.f32")
+    r = run_client("apply", nx, ny, nz, 2, tmp_path / "u.f32", tmp_path / "c.f64", tmp_path / "out.f32",
+                   binary=exe)
     assert r.returncode == 0, r.stderr
     assert "result in u" in r.stdout
     got = np.fromfile(tmp_path / "out.f32", np.float32).reshape(shape)
@@ -75,7 +78,7 @@ def test_c_client_wave_matches_oracle(gpu_lib, tmp_path):
     _coeff_file(tmp_path / "c.f64", co)
     w.tofile(tmp_path / "amp.f32")
     r = run_client("wave", nx, ny, nz, nsteps, repr(dt), repr(dx), tmp_path / "v.f32", tmp_path / "c.f64",
-                   sx, sy, sz, tmp_path / "amp.f32", tmp_path / "out.f32")
+                   sx, sy, sz, tmp_path / "amp.f32", tmp_path / "out.f32", binary=client_binary(str(tmp_path)))
     assert r.returncode == 0, r.stderr
     got = np.fromfile(tmp_path / "out.f32", np.float32).reshape(nz, ny, nx)
     res = oracle.wave_run(co, v, dt, dx, nsteps, src=np.array([[sx, sy, sz]], np.int32),
