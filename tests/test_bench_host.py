@@ -60,3 +60,29 @@ def test_kernel_source_hash_covers_the_kernel_sources(tmp_path, monkeypatch):
         p.write_bytes(data + b"\n")
         assert bench.kernel_source_hash() != h0, name
         p.write_bytes(data)
+
+
+def test_committed_line_keeps_the_reporting_contract():
+    # the latest full bench line kept under profiles/: keys, units and the
+    # arithmetic that ties value, ms_per_step and the roofline together
+    with open(os.path.join(ROOT, "profiles", "bench_1024x1024x512_full.json")) as fh:
+        d = json.load(fh)
+    for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
+              "scaling", "vs_baseline", "dtype", "data", "config", "roofline", "cpu_baseline"):
+        assert k in d, k
+    assert d["n_gpus"] == 1 and d["unit"] == "GPts/s" and d["dtype"] == "f32" and d["data"] == "synthetic"
+    assert d["higher_is_better"] is True and d["vs_baseline"] is None
+    assert "workload" in d["config"] and d["config"]["grid"] == [1024, 1024, 512]
+    steps = d["config"]["time_steps"]
+    # value: points x time steps of one simulation over the wall time of one
+    assert abs(d["value"] - NPTS * steps / (d["ms_per_step"] * 1e-3) / 1e9) <= 1e-3 * d["value"]
+    r = d["roofline"]
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s" and r["peak"] == 8000.0
+    assert r["bytes_per_launch"] == 16 * NPTS
+    assert abs(r["achieved"] - r["bytes_per_launch"] / (r["avg_launch_us"] * 1e-6) / 1e9) <= 0.1
+    assert abs(r["frac"] - r["achieved"] / r["peak"]) <= 1e-3
+    # the launches fit inside the wall time of a simulation
+    assert steps * r["avg_launch_us"] * 1e-3 <= d["ms_per_step"]
+    assert r["traffic"] is None or 16 * NPTS <= r["traffic"] <= 1.1 * 16 * NPTS
+    c = d["cpu_baseline"]
+    assert c["kind"] == "oracle" and c["unit"] == "GPts/s" and c["cores"] >= 1 and c["value"] > 0
